@@ -1,0 +1,70 @@
+"""Seeded input generators: determinism, exact size/depth bounds, text round trip."""
+import numpy as np
+
+from paper_2606_15437_amd import inputs as I
+
+
+def test_splitmix64_reference_values():
+    # SplitMix64 from state 0: the published first outputs of the generator
+    r = I.SplitMix64(0)
+    assert [r.next() for _ in range(3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                            0x06C45D188009454F]
+    z = np.arange(1, 4, dtype=np.uint64) * np.uint64(I.GAMMA)
+    assert [int(x) for x in I.mix64_np(z)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                                0x06C45D188009454F]
+
+
+def test_below_np_matches_exact():
+    rng = I.SplitMix64(5)
+    xs = np.array([rng.next() for _ in range(1000)], dtype=np.uint64)
+    for r in (1, 2, 3, 5, 7, 64, 1000):
+        assert [int(v) for v in I.below_np(xs, r)] == [(int(x) * r) >> 64 for x in xs]
+
+
+def test_config_generators_bounds():
+    for fs, lo, hi, dmax, vmax in ((I.config1_formulas(), 1, 12, 3, 2),
+                                   (I.config2_formulas(), 3, 24, 4, 3),
+                                   (I.config3_formulas(), 3, 40, 6, 2)):
+        for f in fs:
+            assert lo <= len(f) <= hi
+            assert I.modal_depth(f) <= dmax
+            assert all(not I.is_var(op) or op - I.VAR0 < vmax for op in f)
+    assert len(I.config3_formulas()) == 4096
+    assert I.config3_formulas() == I.config3_formulas()
+
+
+def test_text_roundtrip():
+    for f in I.config2_formulas()[:200] + I.config1_formulas():
+        assert I.parse(I.to_text(f)) == f
+    assert I.parse("[](p -> q) -> (<>p -> <>q)") == [2, 3, 9, 10, 2, 11, 3, 11, 9, 9]
+
+
+def test_pack_unpack():
+    fs = I.config1_formulas()
+    code, offs = I.pack(fs)
+    assert I.unpack(code, offs) == fs
+    assert int(offs[-1]) == sum(len(f) for f in fs)
+
+
+def test_frame_family_structure():
+    for n in (6, 7, 8):
+        fr = I.frame_family(n, 4096)
+        assert fr.shape == (4096, n)
+        assert list(fr[0]) == I.path_frame(n)
+        assert list(fr[1]) == [(1 << ((w + 1) % n)) for w in range(n)]
+        kinds = I.family_kind(np.arange(4096))
+        edges = np.array([[bin(int(x)).count("1") for x in row] for row in fr]).sum(1)
+        assert (edges[kinds == I.FAMILY_PATH] == n - 1).all()
+        assert (edges[kinds == I.FAMILY_CYCLE] == n).all()
+        assert (edges[kinds == I.FAMILY_TREE] == n - 1).all()
+        er = edges[kinds == I.FAMILY_ER]
+        assert abs(er.mean() / (n * n) - 0.2) < 0.02
+        # frames are addressable: a window equals the same rows of a longer run
+        assert (I.frame_family(n, 100, start=1000) == fr[1000:1100]).all()
+
+
+def test_retrieval_corpus():
+    c = I.retrieval_corpus(I.SEED_C5_TEST, 3000, n_words=500)
+    assert len(c) == 3000 and len(set(map(tuple, c))) == 3000
+    assert all(len(f) <= 21 for f in c)
+    assert I.alpha(2) in c and I.alpha(3) in c
