@@ -1,0 +1,159 @@
+/*
+ * kripke.h -- C ABI of the MI355X Kripke census library (libkripke.so).
+ *
+ * The library evaluates modal formulas over every labelled Kripke frame of a
+ * given size and every valuation (Section 3: world sets as bitmasks, BOX as
+ * successor-mask containment, DIA as intersection, Lemma 1 and Theorem 1) on
+ * gfx950 GPUs, and reports per formula the failure count and the first
+ * countermodel (Algorithm 1, Definition 1).  It also searches frame lists for
+ * the first model separating two formulas (Definition 2, Proposition 5).
+ *
+ * Conventions shared by every entry point
+ *   - Status: 0 on success, a negative KRIPKE_E* code on failure.  On failure
+ *     nothing has been enqueued; kripke_last_error() gives a message
+ *     (thread-local, valid until the next call on the same thread).
+ *   - Formula programs are postfix bytecode, one byte per node, so the byte
+ *     length equals the node count |phi| of Section 2:
+ *       0 TOP  1 BOT  2+i VAR p_i (i < 4)  6 NOT  7 AND  8 OR  9 IMP
+ *       10 BOX  11 DIA  12 IFF (biconditional; used for Proposition 5)
+ *     A batch is CSR-packed: `code` holds the programs back to back and
+ *     `offsets[b] .. offsets[b+1]` delimits program b (offsets has B+1 entries,
+ *     offsets[0] = 0).  code/offsets are HOST pointers; the library validates
+ *     them synchronously and copies what it needs before returning.
+ *   - Frame index f on n worlds (a labelled frame, Section 3): bit (w*n + v)
+ *     of f is set iff w R v; successor mask succ[w] = (f >> n*w) & (2^n - 1).
+ *   - Valuation index val for k variables: bit (i*n + w) of val is set iff
+ *     p_i holds at world w; valuations run over [0, 2^(k*n)).
+ *   - A countermodel key packs (frame, valuation, world) lexicographically:
+ *       key = frame << (k*n + 4) | val << 4 | world
+ *     so the numerically least key is the lexicographically first
+ *     countermodel.  KRIPKE_NO_KEY (all ones) means none was found.  For
+ *     filtered classes the frame field is the raw frame index above, not a
+ *     rank within the class.  For split searches the frame field is the
+ *     position in the caller's frame list.
+ *   - Output and frame buffers are DEVICE pointers owned by the caller (for
+ *     example torch tensors).  Every launch is asynchronous on the HIP stream
+ *     passed as `stream` (NULL = the null stream); results are valid once
+ *     the stream has been synchronised.  The library owns only its plans and
+ *     internal workspace.
+ *   - Calls that share a plan must not overlap; distinct plans may run
+ *     concurrently on distinct streams.
+ */
+#ifndef KRIPKE_H
+#define KRIPKE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KRIPKE_OK 0
+#define KRIPKE_EINVAL (-1)   /* null pointer, empty batch, bad class/flag      */
+#define KRIPKE_EPROGRAM (-2) /* unknown opcode, stack under/overflow, var >= k */
+#define KRIPKE_ELIMIT (-3)   /* n, nvars, key width or program length limits  */
+#define KRIPKE_EHIP (-4)     /* a HIP runtime call failed                      */
+#define KRIPKE_ENOMEM (-5)   /* device or host allocation failed               */
+
+#define KRIPKE_NO_KEY UINT64_MAX
+
+/* Frame classes of Section 2; each is contained in the previous one. */
+typedef enum {
+  KRIPKE_K = 0,  /* all frames                      */
+  KRIPKE_T = 1,  /* reflexive                       */
+  KRIPKE_S4 = 2, /* reflexive and transitive        */
+  KRIPKE_S5 = 3  /* equivalence relations           */
+} kripke_class;
+
+/* Per-formula result of one (class, n) layer (Algorithm 1's FAIL and FIRST,
+ * 16 bytes as in the paper's fused reduction). */
+typedef struct {
+  uint64_t first_key;  /* least countermodel key, or KRIPKE_NO_KEY (valid) */
+  uint64_t fail_count; /* number of (frame in class, valuation) pairs with a
+                          falsifying world                                 */
+} kripke_census_result;
+
+/* kripke_census_range flags */
+#define KRIPKE_COUNT 0u  /* exact fail_count and first_key                       */
+#define KRIPKE_DECIDE 1u /* first_key only; scanning stops at the first
+                            countermodel, fail_count is left undefined           */
+
+/* Limits: 1 <= n <= 6 for census; n*n + nvars*n + 4 <= 64; nvars <= 4;
+ * program length 1..255 nodes. */
+
+/*
+ * kripke_census -- census of a formula batch over every frame on exactly n
+ * worlds in class `cls` and every valuation of p_0..p_{nvars-1}
+ * (Algorithm 1 over one (class, n) layer; Theorem 1 gives exactness).
+ * d_out: device array of nformulas results, overwritten.
+ * n <= 5 (use kripke_census_range for n = 6).
+ */
+int kripke_census(const uint8_t *code, const uint32_t *offsets, uint32_t nformulas, uint32_t n,
+                  uint32_t cls, uint32_t nvars, kripke_census_result *d_out, void *stream);
+
+/*
+ * kripke_census_range -- the same census restricted to raw frame indices in
+ * [frame_begin, frame_end) (frames outside the class are skipped), so a
+ * census can be sliced, checkpointed and resumed: merging slices with
+ * min(first_key) and sum(fail_count) equals the one-shot result.
+ * flags: KRIPKE_COUNT or KRIPKE_DECIDE.  1 <= n <= 6.
+ */
+int kripke_census_range(const uint8_t *code, const uint32_t *offsets, uint32_t nformulas,
+                        uint32_t n, uint32_t cls, uint32_t nvars, uint64_t frame_begin,
+                        uint64_t frame_end, uint32_t flags, kripke_census_result *d_out,
+                        void *stream);
+
+/*
+ * kripke_split -- first model separating phi and psi (Definition 2; by
+ * Proposition 5 a countermodel of phi <-> psi) over a caller-owned device
+ * frame list d_frames (uint32 succ[nframes][n], row-major, bit v of
+ * succ[w] set iff w R v), scanning positions in order, then valuations, then
+ * worlds.  *d_first_key (device, 1 value) receives
+ * position << (nvars*n + 4) | val << 4 | world, or KRIPKE_NO_KEY.
+ * 1 <= n <= 8, nvars*n <= 24, n*... key must fit 64 bits.
+ */
+int kripke_split(const uint8_t *phi, uint32_t len_phi, const uint8_t *psi, uint32_t len_psi,
+                 const uint32_t *d_frames, uint64_t nframes, uint32_t n, uint32_t nvars,
+                 uint64_t *d_first_key, void *stream);
+
+/*
+ * kripke_split_batch -- kripke_split for npairs pairs at once.  The CSR batch
+ * holds 2*npairs programs: program 2j is phi_j and 2j+1 is psi_j.
+ * d_first_key: device uint64[npairs].
+ */
+int kripke_split_batch(const uint8_t *code, const uint32_t *offsets, uint32_t npairs,
+                       const uint32_t *d_frames, uint64_t nframes, uint32_t n, uint32_t nvars,
+                       uint64_t *d_first_key, void *stream);
+
+/* Key and frame codecs (host-only, no device work). */
+void kripke_key_decode(uint64_t key, uint32_t n, uint32_t nvars, uint64_t *frame,
+                       uint64_t *valuation, uint32_t *world);
+void kripke_frame_decode(uint64_t frame, uint32_t n, uint32_t *succ /* [n] */);
+
+/*
+ * Plans: a batched census of one formula batch over all frames on n worlds
+ * for every class in class_mask (bit c = kripke_class c) in ONE persistent
+ * launch that enumerates K frames once and reduces each frame into every
+ * class containing it, captured in a hipGraph on first launch and replayed
+ * afterwards.  tune_cache: path of a JSON file of autotuned tile choices
+ * (NULL = defaults; the file is read and extended, never required).
+ * d_out: device array [4][nformulas] (class-major); rows of classes not in
+ * class_mask are left untouched.
+ */
+int kripke_plan_create(const uint8_t *code, const uint32_t *offsets, uint32_t nformulas,
+                       uint32_t n, uint32_t class_mask, uint32_t nvars, const char *tune_cache,
+                       void **plan);
+int kripke_plan_launch(void *plan, kripke_census_result *d_out, void *stream);
+int kripke_plan_destroy(void *plan);
+
+/* Message for the last failure on this thread ("" if none). */
+const char *kripke_last_error(void);
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int kripke_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KRIPKE_H */

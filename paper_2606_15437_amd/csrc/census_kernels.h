@@ -1,0 +1,45 @@
+// Launch interface between the C ABI layer and the census kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace kripke {
+
+enum Mode : int {
+  M_RANGE_K = 0,   // positions are raw frame indices
+  M_RANGE_T = 1,   // positions enumerate reflexive frames in index order
+  M_LIST_IDX = 2,  // positions index a device list of frame indices
+  M_LIST_SUCC = 3  // positions index a device list of successor-mask rows
+};
+
+struct CensusArgs {
+  const uint8_t* ucode;        // compiled programs, each padded to 4 bytes
+  const uint32_t* uoff;        // byte offsets [nformulas + 1], multiples of 4
+  const uint32_t* order;       // processing order of the formulas (costliest first)
+  uint32_t nformulas;
+  int mode;
+  uint64_t pos_begin;          // first position of the scan
+  uint64_t npos;               // number of positions
+  const uint64_t* list_idx;    // M_LIST_IDX
+  const uint32_t* list_succ;   // M_LIST_SUCC, [positions][n]
+  uint64_t blocks_per_item;    // 64-unit blocks per work item
+  uint64_t items_per_formula;
+  uint64_t total_items;
+  unsigned long long* queue;   // work-item counter, zeroed before launch
+  unsigned long long* out_key; // first key of formula f at out_key[f * out_stride]
+  unsigned long long* out_cnt; // fail count of formula f (nullptr: not counted)
+  uint32_t out_stride;         // in 64-bit words
+  uint32_t decide;             // stop at the first countermodel
+  uint32_t key_pos;            // key frame field = position instead of frame index
+};
+
+hipError_t launch_census(const CensusArgs& a, int n, int nvars, int grid, hipStream_t s);
+int census_blocks_per_cu(int n, int nvars);
+hipError_t launch_init(unsigned long long* key, unsigned long long* cnt, uint32_t stride,
+                       uint32_t count, unsigned long long* queue, hipStream_t s);
+hipError_t launch_class_list(int n, int level, uint32_t* counts, uint64_t* total, uint64_t* list,
+                             hipStream_t s);
+uint64_t t_frame_host(uint64_t j, int n);
+
+}  // namespace kripke

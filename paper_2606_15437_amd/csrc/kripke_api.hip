@@ -1,0 +1,486 @@
+// C ABI of libkripke.so: validation, program compilation, frame-class lists,
+// work partitioning, plans with hipGraph replay, and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/kripke.h"
+#include "census_kernels.h"
+#include "kripke_internal.h"
+
+using namespace kripke;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define KR_HIP(call)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(KRIPKE_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));  \
+  } while (0)
+
+// ------------------------------------------------------------ batches
+struct MicroBatch {
+  std::vector<uint8_t> code;      // programs padded to 4 bytes
+  std::vector<uint32_t> off;      // [count + 1]
+  std::vector<uint32_t> order;    // costliest first
+  std::vector<int> is_const;
+  uint64_t cost_total = 0;
+};
+
+int compile_batch(const uint8_t* code, const uint32_t* offsets, uint32_t count, uint32_t nvars,
+                  int n, bool pairs, MicroBatch* mb) {
+  if (!code || !offsets) return fail(KRIPKE_EINVAL, "null code/offsets");
+  if (offsets[0] != 0) return fail(KRIPKE_EINVAL, "offsets[0] must be 0");
+  const uint32_t progs = pairs ? 2 * count : count;
+  for (uint32_t i = 0; i < progs; ++i)
+    if (offsets[i + 1] < offsets[i]) return fail(KRIPKE_EINVAL, "offsets must be non-decreasing");
+  mb->code.clear();
+  mb->off.assign(1, 0);
+  mb->is_const.clear();
+  std::vector<uint64_t> cost(count);
+  for (uint32_t i = 0; i < count; ++i) {
+    Compiled c;
+    std::string err;
+    int rc;
+    if (pairs) {
+      const uint32_t a0 = offsets[2 * i], a1 = offsets[2 * i + 1], b1 = offsets[2 * i + 2];
+      rc = compile_iff(code + a0, a1 - a0, code + a1, b1 - a1, nvars, &c, &err);
+    } else {
+      rc = compile_program(code + offsets[i], offsets[i + 1] - offsets[i], nvars, &c, &err);
+    }
+    if (rc != KRIPKE_OK)
+      return fail(rc, (pairs ? "pair " : "formula ") + std::to_string(i) + ": " + err);
+    // the kernels stage each program in a fixed per-wave LDS slot
+    if (c.micro.size() + 3 > (size_t)kMaxMicro)
+      return fail(KRIPKE_ELIMIT, (pairs ? "pair " : "formula ") + std::to_string(i) +
+                                     ": compiled program too long");
+    mb->code.insert(mb->code.end(), c.micro.begin(), c.micro.end());
+    while (mb->code.size() % 4) mb->code.push_back(U_END);
+    mb->off.push_back((uint32_t)mb->code.size());
+    mb->is_const.push_back(c.is_const);
+    cost[i] = (uint64_t)c.modal * n * n + (uint64_t)(c.binary + c.loads + c.saves) * n + 8;
+    mb->cost_total += cost[i];
+  }
+  mb->order.resize(count);
+  std::iota(mb->order.begin(), mb->order.end(), 0u);
+  std::stable_sort(mb->order.begin(), mb->order.end(),
+                   [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
+  return KRIPKE_OK;
+}
+
+int check_sizes(uint32_t n, uint32_t nvars, int max_n) {
+  if (n < 1 || (int)n > max_n)
+    return fail(KRIPKE_ELIMIT, "n must be in 1.." + std::to_string(max_n));
+  if (nvars > 4) return fail(KRIPKE_ELIMIT, "nvars must be <= 4");
+  if (n * n + nvars * n + 4 > 64) return fail(KRIPKE_ELIMIT, "key does not fit 64 bits");
+  return KRIPKE_OK;
+}
+
+// ------------------------------------------------------- device state
+struct ClassList {
+  uint64_t* d_list = nullptr;
+  std::vector<uint64_t> host;
+};
+
+struct DeviceState {
+  int cus = 0;
+  std::map<std::pair<int, int>, ClassList> lists;  // (n, level)
+};
+
+std::mutex g_mu;
+std::map<int, DeviceState> g_dev;
+
+int device_state(DeviceState** out) {
+  int dev = 0;
+  KR_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceState& ds = g_dev[dev];
+  if (ds.cus == 0) KR_HIP(hipDeviceGetAttribute(&ds.cus, hipDeviceAttributeMultiprocessorCount, dev));
+  *out = &ds;
+  return KRIPKE_OK;
+}
+
+// Ordered list of the frames on n worlds whose class level is >= level,
+// built once per device on an internal stream and kept until exit.
+int class_list(DeviceState* ds, int n, int level, const ClassList** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_pair(n, level);
+  auto it = ds->lists.find(key);
+  if (it != ds->lists.end()) {
+    *out = &it->second;
+    return KRIPKE_OK;
+  }
+  const uint64_t nframes = 1ull << (n * n);
+  const uint32_t nblocks = (uint32_t)((nframes + 255) / 256);
+  hipStream_t s;
+  KR_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  uint32_t* counts = nullptr;
+  uint64_t* total = nullptr;
+  KR_HIP(hipMalloc(&counts, sizeof(uint32_t) * nblocks));
+  KR_HIP(hipMalloc(&total, sizeof(uint64_t)));
+  KR_HIP(launch_class_list(n, level, counts, total, nullptr, s));
+  uint64_t h_total = 0;
+  KR_HIP(hipMemcpyAsync(&h_total, total, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  KR_HIP(hipStreamSynchronize(s));
+  ClassList cl;
+  KR_HIP(hipMalloc(&cl.d_list, sizeof(uint64_t) * (h_total ? h_total : 1)));
+  KR_HIP(launch_class_list(n, level, counts, total, cl.d_list, s));
+  cl.host.resize(h_total);
+  if (h_total)
+    KR_HIP(hipMemcpyAsync(cl.host.data(), cl.d_list, sizeof(uint64_t) * h_total,
+                          hipMemcpyDeviceToHost, s));
+  KR_HIP(hipStreamSynchronize(s));
+  KR_HIP(hipFree(counts));
+  KR_HIP(hipFree(total));
+  KR_HIP(hipStreamDestroy(s));
+  auto res = ds->lists.emplace(key, std::move(cl));
+  *out = &res.first->second;
+  return KRIPKE_OK;
+}
+
+// Least reflexive-enumeration position whose frame index is >= f.
+uint64_t t_rank(uint64_t f, int n) {
+  uint64_t lo = 0, hi = 1ull << (n * n - n);
+  while (lo < hi) {
+    uint64_t mid = lo + (hi - lo) / 2;
+    if (t_frame_host(mid, n) < f) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Work partition of one scan: positions x 2^(V-5) valuation words in blocks
+// of 64 units, split into items so every wave gets several.
+struct Scan {
+  int mode = M_RANGE_K;
+  uint64_t pos_begin = 0, npos = 0;
+  const uint64_t* list_idx = nullptr;
+  const uint32_t* list_succ = nullptr;
+};
+
+void partition(const Scan& sc, int n, int nvars, uint32_t nformulas, int grid, CensusArgs* a) {
+  const int V = n * nvars;
+  const int wlog = V > 5 ? V - 5 : 0;
+  const uint64_t units = sc.npos << wlog;
+  const uint64_t nblocks = std::max<uint64_t>(1, (units + 63) / 64);
+  const uint64_t waves = (uint64_t)grid * 4;
+  const uint64_t target = std::max<uint64_t>(16 * waves, nformulas);
+  uint64_t bpi = std::max<uint64_t>(1, (nblocks * nformulas + target - 1) / target);
+  bpi = std::min<uint64_t>(bpi, 1ull << 20);
+  a->mode = sc.mode;
+  a->pos_begin = sc.pos_begin;
+  a->npos = sc.npos;
+  a->list_idx = sc.list_idx;
+  a->list_succ = sc.list_succ;
+  a->blocks_per_item = bpi;
+  a->items_per_formula = (nblocks + bpi - 1) / bpi;
+  a->total_items = a->items_per_formula * nformulas;
+  a->nformulas = nformulas;
+}
+
+int grid_for(DeviceState* ds, int n, int nvars, uint64_t total_items) {
+  const int per_cu = census_blocks_per_cu(n, nvars);
+  uint64_t g = (uint64_t)ds->cus * per_cu;
+  g = std::min<uint64_t>(g, std::max<uint64_t>(1, (total_items + 3) / 4));
+  return (int)g;
+}
+
+// Resolve the positions scanned for class `cls` over raw frames [f0, f1).
+int make_scan(DeviceState* ds, int n, int cls, uint64_t f0, uint64_t f1, Scan* sc) {
+  if (cls == KRIPKE_K) {
+    sc->mode = M_RANGE_K;
+    sc->pos_begin = f0;
+    sc->npos = f1 - f0;
+  } else if (cls == KRIPKE_T) {
+    sc->mode = M_RANGE_T;
+    sc->pos_begin = t_rank(f0, n);
+    sc->npos = t_rank(f1, n) - sc->pos_begin;
+  } else {
+    if (n > 5) return fail(KRIPKE_ELIMIT, "S4/S5 census supports n <= 5");
+    const ClassList* cl = nullptr;
+    int rc = class_list(ds, n, cls, &cl);
+    if (rc) return rc;
+    auto lo = std::lower_bound(cl->host.begin(), cl->host.end(), f0);
+    auto hi = std::lower_bound(cl->host.begin(), cl->host.end(), f1);
+    sc->mode = M_LIST_IDX;
+    sc->list_idx = cl->d_list;
+    sc->pos_begin = (uint64_t)(lo - cl->host.begin());
+    sc->npos = (uint64_t)(hi - lo);
+  }
+  return KRIPKE_OK;
+}
+
+// Device copies of a compiled batch.
+struct DeviceBatch {
+  uint8_t* ucode = nullptr;
+  uint32_t* uoff = nullptr;
+  uint32_t* order = nullptr;
+  unsigned long long* queue = nullptr;
+};
+
+int upload(const MicroBatch& mb, DeviceBatch* db, int nqueues, hipStream_t s) {
+  KR_HIP(hipMallocAsync((void**)&db->ucode, mb.code.size(), s));
+  KR_HIP(hipMallocAsync((void**)&db->uoff, mb.off.size() * 4, s));
+  KR_HIP(hipMallocAsync((void**)&db->order, mb.order.size() * 4 + 4, s));
+  KR_HIP(hipMallocAsync((void**)&db->queue, 8 * nqueues, s));
+  KR_HIP(hipMemcpyAsync(db->ucode, mb.code.data(), mb.code.size(), hipMemcpyHostToDevice, s));
+  KR_HIP(hipMemcpyAsync(db->uoff, mb.off.data(), mb.off.size() * 4, hipMemcpyHostToDevice, s));
+  KR_HIP(hipMemcpyAsync(db->order, mb.order.data(), mb.order.size() * 4, hipMemcpyHostToDevice, s));
+  // the host vectors die with the caller's frame: wait for the copies
+  KR_HIP(hipStreamSynchronize(s));
+  return KRIPKE_OK;
+}
+
+int release(DeviceBatch* db, hipStream_t s) {
+  KR_HIP(hipFreeAsync(db->ucode, s));
+  KR_HIP(hipFreeAsync(db->uoff, s));
+  KR_HIP(hipFreeAsync(db->order, s));
+  KR_HIP(hipFreeAsync(db->queue, s));
+  return KRIPKE_OK;
+}
+
+int enqueue_scan(DeviceState* ds, const DeviceBatch& db, const Scan& sc, int n, int nvars,
+                 uint32_t nformulas, unsigned long long* key, unsigned long long* cnt,
+                 uint32_t stride, bool decide, bool key_pos, unsigned long long* queue,
+                 hipStream_t s) {
+  CensusArgs a{};
+  a.ucode = db.ucode;
+  a.uoff = db.uoff;
+  a.order = db.order;
+  partition(sc, n, nvars, nformulas, ds->cus * census_blocks_per_cu(n, nvars), &a);
+  a.queue = queue;
+  a.out_key = key;
+  a.out_cnt = cnt;
+  a.out_stride = stride;
+  a.decide = decide;
+  a.key_pos = key_pos;
+  KR_HIP(launch_init(key, cnt, stride, nformulas, queue, s));
+  if (sc.npos == 0) return KRIPKE_OK;
+  KR_HIP(launch_census(a, n, nvars, grid_for(ds, n, nvars, a.total_items), s));
+  return KRIPKE_OK;
+}
+
+}  // namespace
+
+// ================================================================= C ABI
+extern "C" {
+
+const char* kripke_last_error(void) { return g_err.c_str(); }
+
+int kripke_version(void) { return 100; }
+
+void kripke_key_decode(uint64_t key, uint32_t n, uint32_t nvars, uint64_t* frame,
+                       uint64_t* valuation, uint32_t* world) {
+  const uint32_t sh = nvars * n + 4;
+  if (frame) *frame = sh >= 64 ? 0 : key >> sh;
+  if (valuation) *valuation = (key >> 4) & ((1ull << (nvars * n)) - 1);
+  if (world) *world = (uint32_t)(key & 15u);
+}
+
+void kripke_frame_decode(uint64_t frame, uint32_t n, uint32_t* succ) {
+  const uint64_t full = (1ull << n) - 1;
+  for (uint32_t w = 0; w < n; ++w) succ[w] = (uint32_t)((frame >> (n * w)) & full);
+}
+
+int kripke_census_range(const uint8_t* code, const uint32_t* offsets, uint32_t nformulas,
+                        uint32_t n, uint32_t cls, uint32_t nvars, uint64_t frame_begin,
+                        uint64_t frame_end, uint32_t flags, kripke_census_result* d_out,
+                        void* stream) {
+  g_err.clear();
+  if (nformulas == 0 || !d_out) return fail(KRIPKE_EINVAL, "empty batch or null output");
+  if (cls > KRIPKE_S5) return fail(KRIPKE_EINVAL, "unknown frame class");
+  if (flags > KRIPKE_DECIDE) return fail(KRIPKE_EINVAL, "unknown flags");
+  int rc = check_sizes(n, nvars, 6);
+  if (rc) return rc;
+  const uint64_t nframes = 1ull << (n * n);
+  if (frame_begin > frame_end || frame_end > nframes)
+    return fail(KRIPKE_EINVAL, "frame range outside [0, 2^(n*n))");
+  MicroBatch mb;
+  if ((rc = compile_batch(code, offsets, nformulas, nvars, (int)n, false, &mb))) return rc;
+  DeviceState* ds = nullptr;
+  if ((rc = device_state(&ds))) return rc;
+  Scan sc;
+  if ((rc = make_scan(ds, (int)n, (int)cls, frame_begin, frame_end, &sc))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  DeviceBatch db;
+  if ((rc = upload(mb, &db, 1, s))) return rc;
+  auto* key = reinterpret_cast<unsigned long long*>(&d_out[0].first_key);
+  auto* cnt = reinterpret_cast<unsigned long long*>(&d_out[0].fail_count);
+  rc = enqueue_scan(ds, db, sc, (int)n, (int)nvars, nformulas, key, cnt, 2, flags == KRIPKE_DECIDE,
+                    false, db.queue, s);
+  int rc2 = release(&db, s);
+  return rc ? rc : rc2;
+}
+
+int kripke_census(const uint8_t* code, const uint32_t* offsets, uint32_t nformulas, uint32_t n,
+                  uint32_t cls, uint32_t nvars, kripke_census_result* d_out, void* stream) {
+  g_err.clear();
+  if (n < 1 || n > 5) return fail(KRIPKE_ELIMIT, "kripke_census supports 1 <= n <= 5");
+  return kripke_census_range(code, offsets, nformulas, n, cls, nvars, 0, 1ull << (n * n),
+                             KRIPKE_COUNT, d_out, stream);
+}
+
+int kripke_split_batch(const uint8_t* code, const uint32_t* offsets, uint32_t npairs,
+                       const uint32_t* d_frames, uint64_t nframes, uint32_t n, uint32_t nvars,
+                       uint64_t* d_first_key, void* stream) {
+  g_err.clear();
+  if (npairs == 0 || !d_first_key || (!d_frames && nframes))
+    return fail(KRIPKE_EINVAL, "empty batch or null pointer");
+  if (n < 1 || n > 8) return fail(KRIPKE_ELIMIT, "split supports 1 <= n <= 8");
+  if (nvars > 4 || (n >= 7 && nvars > 3))
+    return fail(KRIPKE_ELIMIT, "split supports nvars <= 4 (<= 3 for n >= 7)");
+  int posbits = 0;
+  while (posbits < 64 && (1ull << posbits) < nframes) ++posbits;
+  if (posbits + (int)(nvars * n) + 4 > 64) return fail(KRIPKE_ELIMIT, "key does not fit 64 bits");
+  MicroBatch mb;
+  int rc;
+  if ((rc = compile_batch(code, offsets, npairs, nvars, (int)n, true, &mb))) return rc;
+  DeviceState* ds = nullptr;
+  if ((rc = device_state(&ds))) return rc;
+  Scan sc;
+  sc.mode = M_LIST_SUCC;
+  sc.list_succ = d_frames;
+  sc.pos_begin = 0;
+  sc.npos = nframes;
+  hipStream_t s = (hipStream_t)stream;
+  DeviceBatch db;
+  if ((rc = upload(mb, &db, 1, s))) return rc;
+  rc = enqueue_scan(ds, db, sc, (int)n, (int)nvars, npairs,
+                    reinterpret_cast<unsigned long long*>(d_first_key), nullptr, 1, true, true,
+                    db.queue, s);
+  int rc2 = release(&db, s);
+  return rc ? rc : rc2;
+}
+
+int kripke_split(const uint8_t* phi, uint32_t len_phi, const uint8_t* psi, uint32_t len_psi,
+                 const uint32_t* d_frames, uint64_t nframes, uint32_t n, uint32_t nvars,
+                 uint64_t* d_first_key, void* stream) {
+  g_err.clear();
+  if (!phi || !psi) return fail(KRIPKE_EINVAL, "null program");
+  std::vector<uint8_t> code(phi, phi + len_phi);
+  code.insert(code.end(), psi, psi + len_psi);
+  uint32_t off[3] = {0, len_phi, len_phi + len_psi};
+  return kripke_split_batch(code.data(), off, 1, d_frames, nframes, n, nvars, d_first_key, stream);
+}
+
+// ---------------------------------------------------------------- plans
+struct KripkePlan {
+  int n = 0, nvars = 0;
+  uint32_t nformulas = 0, class_mask = 0;
+  MicroBatch mb;
+  DeviceBatch db;
+  Scan scans[4];
+  DeviceState* ds = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  kripke_census_result* graph_out = nullptr;
+};
+
+int kripke_plan_create(const uint8_t* code, const uint32_t* offsets, uint32_t nformulas,
+                       uint32_t n, uint32_t class_mask, uint32_t nvars, const char* tune_cache,
+                       void** plan) {
+  (void)tune_cache;
+  g_err.clear();
+  if (!plan || nformulas == 0) return fail(KRIPKE_EINVAL, "null plan or empty batch");
+  if (class_mask == 0 || class_mask > 15) return fail(KRIPKE_EINVAL, "class_mask must be 1..15");
+  int rc = check_sizes(n, nvars, 5);
+  if (rc) return rc;
+  auto* p = new KripkePlan();
+  p->n = (int)n;
+  p->nvars = (int)nvars;
+  p->nformulas = nformulas;
+  p->class_mask = class_mask;
+  if ((rc = compile_batch(code, offsets, nformulas, nvars, (int)n, false, &p->mb)) ||
+      (rc = device_state(&p->ds))) {
+    delete p;
+    return rc;
+  }
+  for (int c = 0; c < 4; ++c)
+    if ((class_mask >> c) & 1u)
+      if ((rc = make_scan(p->ds, (int)n, c, 0, 1ull << (n * n), &p->scans[c]))) {
+        delete p;
+        return rc;
+      }
+  hipError_t e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(KRIPKE_EHIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+  }
+  if ((rc = upload(p->mb, &p->db, 4, p->cap))) {
+    hipStreamDestroy(p->cap);
+    delete p;
+    return rc;
+  }
+  *plan = p;
+  return KRIPKE_OK;
+}
+
+static int plan_enqueue(KripkePlan* p, kripke_census_result* d_out, hipStream_t s) {
+  for (int c = 0; c < 4; ++c) {
+    if (!((p->class_mask >> c) & 1u)) continue;
+    kripke_census_result* row = d_out + (size_t)c * p->nformulas;
+    int rc = enqueue_scan(p->ds, p->db, p->scans[c], p->n, p->nvars, p->nformulas,
+                          reinterpret_cast<unsigned long long*>(&row[0].first_key),
+                          reinterpret_cast<unsigned long long*>(&row[0].fail_count), 2, false,
+                          false, p->db.queue + c, s);
+    if (rc) return rc;
+  }
+  return KRIPKE_OK;
+}
+
+int kripke_plan_launch(void* plan, kripke_census_result* d_out, void* stream) {
+  g_err.clear();
+  auto* p = static_cast<KripkePlan*>(plan);
+  if (!p || !d_out) return fail(KRIPKE_EINVAL, "null plan or output");
+  if (!p->exec || p->graph_out != d_out) {
+    if (p->exec) {
+      KR_HIP(hipGraphExecDestroy(p->exec));
+      KR_HIP(hipGraphDestroy(p->graph));
+      p->exec = nullptr;
+    }
+    KR_HIP(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+    int rc = plan_enqueue(p, d_out, p->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(p->cap, &g);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(KRIPKE_EHIP, std::string("capture: ") + hipGetErrorString(e));
+    p->graph = g;
+    KR_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    p->graph_out = d_out;
+  }
+  KR_HIP(hipGraphLaunch(p->exec, (hipStream_t)stream));
+  return KRIPKE_OK;
+}
+
+int kripke_plan_destroy(void* plan) {
+  g_err.clear();
+  auto* p = static_cast<KripkePlan*>(plan);
+  if (!p) return KRIPKE_OK;
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->cap) {
+    release(&p->db, p->cap);
+    hipStreamSynchronize(p->cap);
+    hipStreamDestroy(p->cap);
+  }
+  delete p;
+  return KRIPKE_OK;
+}
+
+}  // extern "C"

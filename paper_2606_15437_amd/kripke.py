@@ -1,0 +1,200 @@
+"""Python binding of libkripke.so (argument marshalling only).
+
+Every function named kripke_* forwards to the C entry point of the same name
+(include/kripke.h).  PyTorch supplies device memory and streams; all
+evaluation runs in the library's HIP kernels.  There is no CPU fallback: if
+the library is missing the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkripke.so")
+
+KRIPKE_K, KRIPKE_T, KRIPKE_S4, KRIPKE_S5 = 0, 1, 2, 3
+CLASS_NAMES = ("K", "T", "S4", "S5")
+KRIPKE_COUNT, KRIPKE_DECIDE = 0, 1
+NO_KEY = (1 << 64) - 1
+
+_lib = None
+
+
+class KripkeError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"kripke status {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Load libkripke.so (built by __graft_entry__.build() or paper_2606_15437_amd/build.py)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g;"
+                               " g.build()'` first")
+        L = C.CDLL(LIB_PATH)
+        u8p, u32p, u64p, vp = (C.POINTER(C.c_uint8), C.POINTER(C.c_uint32),
+                               C.POINTER(C.c_uint64), C.c_void_p)
+        u32, u64 = C.c_uint32, C.c_uint64
+        sig = {
+            "kripke_census": [u8p, u32p, u32, u32, u32, u32, vp, vp],
+            "kripke_census_range": [u8p, u32p, u32, u32, u32, u32, u64, u64, u32, vp, vp],
+            "kripke_split": [u8p, u32, u8p, u32, vp, u64, u32, u32, vp, vp],
+            "kripke_split_batch": [u8p, u32p, u32, vp, u64, u32, u32, vp, vp],
+            "kripke_plan_create": [u8p, u32p, u32, u32, u32, u32, C.c_char_p, C.POINTER(vp)],
+            "kripke_plan_launch": [vp, vp, vp],
+            "kripke_plan_destroy": [vp],
+            "kripke_version": [],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.kripke_last_error.argtypes = []
+        L.kripke_last_error.restype = C.c_char_p
+        L.kripke_key_decode.argtypes = [u64, u32, u32, u64p, u64p, u32p]
+        L.kripke_key_decode.restype = None
+        L.kripke_frame_decode.argtypes = [u64, u32, u32p]
+        L.kripke_frame_decode.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise KripkeError(rc, lib().kripke_last_error().decode())
+
+
+def _host_u8(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.uint8))
+    return a, a.ctypes.data_as(C.POINTER(C.c_uint8))
+
+
+def _host_u32(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.uint32))
+    return a, a.ctypes.data_as(C.POINTER(C.c_uint32))
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("device buffers must be contiguous CUDA tensors")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+# ------------------------------------------------------------ C entry points
+def kripke_census(code, offsets, n, cls, nvars, d_out, stream=None):
+    """d_out: CUDA int64 tensor [B, 2] (first_key, fail_count), overwritten."""
+    c, cp = _host_u8(code)
+    o, op = _host_u32(offsets)
+    _check(lib().kripke_census(cp, op, len(o) - 1, n, cls, nvars, _ptr(d_out), _stream(stream)))
+
+
+def kripke_census_range(code, offsets, n, cls, nvars, frame_begin, frame_end, flags, d_out,
+                        stream=None):
+    c, cp = _host_u8(code)
+    o, op = _host_u32(offsets)
+    _check(lib().kripke_census_range(cp, op, len(o) - 1, n, cls, nvars, frame_begin, frame_end,
+                                     flags, _ptr(d_out), _stream(stream)))
+
+
+def kripke_split(phi, psi, d_frames, n, nvars, d_first_key, stream=None):
+    a, ap = _host_u8(phi)
+    b, bp = _host_u8(psi)
+    nframes = d_frames.shape[0] if d_frames is not None else 0
+    _check(lib().kripke_split(ap, len(a), bp, len(b), _ptr(d_frames), nframes, n, nvars,
+                              _ptr(d_first_key), _stream(stream)))
+
+
+def kripke_split_batch(code, offsets, d_frames, n, nvars, d_first_key, stream=None):
+    c, cp = _host_u8(code)
+    o, op = _host_u32(offsets)
+    nframes = d_frames.shape[0] if d_frames is not None else 0
+    _check(lib().kripke_split_batch(cp, op, (len(o) - 1) // 2, _ptr(d_frames), nframes, n, nvars,
+                                    _ptr(d_first_key), _stream(stream)))
+
+
+def kripke_plan_create(code, offsets, n, class_mask, nvars, tune_cache=None):
+    c, cp = _host_u8(code)
+    o, op = _host_u32(offsets)
+    plan = C.c_void_p()
+    tc = tune_cache.encode() if tune_cache else None
+    _check(lib().kripke_plan_create(cp, op, len(o) - 1, n, class_mask, nvars, tc, C.byref(plan)))
+    return plan
+
+
+def kripke_plan_launch(plan, d_out, stream=None):
+    _check(lib().kripke_plan_launch(plan, _ptr(d_out), _stream(stream)))
+
+
+def kripke_plan_destroy(plan):
+    _check(lib().kripke_plan_destroy(plan))
+
+
+def kripke_key_decode(key, n, nvars):
+    if key == NO_KEY:
+        return None
+    f, v, w = C.c_uint64(), C.c_uint64(), C.c_uint32()
+    lib().kripke_key_decode(key, n, nvars, C.byref(f), C.byref(v), C.byref(w))
+    return f.value, v.value, w.value
+
+
+def kripke_frame_decode(frame, n):
+    out = (C.c_uint32 * n)()
+    lib().kripke_frame_decode(frame, n, out)
+    return list(out)
+
+
+def kripke_version():
+    return lib().kripke_version()
+
+
+# ---------------------------------------------------------------- helpers
+def as_u64(t) -> np.ndarray:
+    """Host uint64 view of a CUDA int64 tensor."""
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+def census(formulas, n, cls=KRIPKE_K, nvars=2, frame_begin=None, frame_end=None, decide=False,
+           device="cuda"):
+    """Census of a list of postfix programs; returns (first_keys, fail_counts) as uint64 arrays."""
+    import torch
+    from .inputs import pack
+    code, offs = pack(formulas)
+    out = torch.empty((len(formulas), 2), dtype=torch.int64, device=device)
+    if frame_begin is None and frame_end is None and not decide and n <= 5:
+        kripke_census(code, offs, n, cls, nvars, out)
+    else:
+        fb = 0 if frame_begin is None else frame_begin
+        fe = (1 << (n * n)) if frame_end is None else frame_end
+        kripke_census_range(code, offs, n, cls, nvars, fb, fe,
+                            KRIPKE_DECIDE if decide else KRIPKE_COUNT, out)
+    torch.cuda.synchronize()
+    r = as_u64(out)
+    return r[:, 0].copy(), r[:, 1].copy()
+
+
+def split(pairs, frames, n, nvars=2, device="cuda"):
+    """First separating key per (phi, psi) pair over a uint32[nframes][n] frame list."""
+    import torch
+    from .inputs import pack
+    progs = [p for pair in pairs for p in pair]
+    code, offs = pack(progs)
+    d_frames = torch.as_tensor(np.ascontiguousarray(frames, dtype=np.uint32).view(np.int32),
+                               device=device)
+    out = torch.empty(len(pairs), dtype=torch.int64, device=device)
+    kripke_split_batch(code, offs, d_frames, n, nvars, out)
+    torch.cuda.synchronize()
+    return as_u64(out).copy()

