@@ -11,8 +11,12 @@ SOURCES = ["census_kernels.hip", "fast_kernels.hip", "mlp_kernels.hip", "kripke_
            "kripke_compile.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed-FP32 instructions are disabled for all device code.
+# The interpreters dispatch on wave-uniform opcodes; letting the structurizer
+# skip uniform regions keeps their switch from being rewritten into flow
+# blocks full of register copies.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-structurizecfg-skip-uniform-regions=true"]
 
 
 def _compile(src: str, verbose: bool) -> str:

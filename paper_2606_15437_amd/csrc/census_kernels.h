@@ -34,6 +34,34 @@ struct CensusArgs {
   uint32_t key_pos;            // key frame field = position instead of frame index
 };
 
+// Arguments of the wave-uniform-frame kernel.  Positions are frame indices
+// (mode 0, class K) or ranks of reflexive frames (mode 1, class T); a block
+// holds 2^fast_block_log2() consecutive positions.
+struct FastArgs {
+  const uint8_t* ucode;
+  const uint32_t* uoff;
+  const uint32_t* order;
+  uint32_t nformulas;
+  uint64_t pos_begin, pos_end;  // scanned positions [pos_begin, pos_end)
+  uint64_t blk_begin, nblk;     // blocks covering them
+  uint64_t blocks_per_item, items_per_formula, total_items;
+  unsigned long long* queue;
+  const uint32_t* levels;       // fused: 2-bit class level per frame, 16 per word
+  unsigned long long* out_key;  // class-0 row; class k at + k * class_stride
+  unsigned long long* out_cnt;
+  uint32_t out_stride;
+  uint64_t class_stride;
+  uint32_t decide;
+};
+
+bool fast_available(int n, int nvars, int ls, int mode, bool fused);
+int fast_block_log2(int n, int nvars, int ls);
+hipError_t launch_fast(const FastArgs& a, int n, int nvars, int ls, int mode, bool fused, int grid,
+                       hipStream_t s);
+int fast_blocks_per_cu(int n, int nvars, int ls, int mode, bool fused);
+hipError_t launch_levels(int n, uint32_t* levels, hipStream_t s);
+uint64_t refl_frame_host(uint64_t j, int n);
+
 hipError_t launch_census(const CensusArgs& a, int n, int nvars, int grid, hipStream_t s);
 int census_blocks_per_cu(int n, int nvars);
 hipError_t launch_init(unsigned long long* key, unsigned long long* cnt, uint32_t stride,

@@ -1,0 +1,522 @@
+// Fast census kernel for gfx950: wave-uniform frames.
+//
+// The generic kernel gives every lane its own frame, so every relation word
+// R(w,v) is a vector register rebuilt per block.  Here a wavefront works on
+// a block of 2^(LF+LS) consecutive frames (in class enumeration order):
+//   - the 5 in-word bits and the low lane bits index valuations, exactly as
+//     in the generic kernel (all valuations of a frame sit in one wave when
+//     n*k <= 11);
+//   - the remaining LF lane bits index LF frame positions (per-lane relation
+//     words, fixed for the whole kernel);
+//   - LS "set" bits index the next frame positions: every lane evaluates the
+//     formula on 2^LS frames at once, and the relation words of those
+//     positions are compile-time constants per set;
+//   - all other relation bits are shared by the whole block: scalar
+//     registers, decoded once per block by the scalar unit.
+// So Lemma 1's DIA/BOX cost one VALU op per (world, successor) term with a
+// scalar operand, constant terms fold away, and one scalar interpreter
+// dispatch drives 2^LS sets of VALU work.
+//
+// Frame enumeration: mode K scans raw frame indices; mode T scans reflexive
+// frames in index order (positions deposit into the off-diagonal bits).  In
+// mode K with `fused`, each frame also reduces into the classes T, S4 and S5
+// it belongs to (a precomputed 2-bit class level per frame), so one pass over
+// the K frames yields the census of all four classes.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "census_kernels.h"
+#include "kripke_internal.h"
+
+namespace kripke {
+namespace {
+
+__host__ __device__ constexpr uint32_t pattern(int b) {
+  return b == 0 ? 0xAAAAAAAAu : b == 1 ? 0xCCCCCCCCu : b == 2 ? 0xF0F0F0F0u
+       : b == 3 ? 0xFF00FF00u : 0xFFFF0000u;
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int lane) {
+  uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, lane);
+  uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__host__ __device__ __forceinline__ uint64_t refl_frame(uint64_t j, int n) {
+  uint64_t full = (1ull << n) - 1, f = 0;
+  for (int w = 0; w < n; ++w) f |= 1ull << (w * n + w);
+  for (int k = 0; k + 1 < n; ++k) f |= ((j >> (k * n)) & full) << (k * (n + 1) + 1);
+  return f;
+}
+
+enum Role { R_UNIFORM = 0, R_LANE = 1, R_SET = 2, R_ONE = 3 };
+
+template <int N, int MODE>
+__host__ __device__ constexpr int free_rank(int p) {
+  // rank of position p among the enumerated (free) positions
+  return MODE == 0 ? p : p - p / (N + 1) - 1;
+}
+
+template <int N, int MODE, int LF, int LS>
+__host__ __device__ constexpr int role(int p) {
+  if (MODE == 1 && p % (N + 1) == 0) return R_ONE;
+  const int r = free_rank<N, MODE>(p);
+  return r < LF ? R_LANE : r < LF + LS ? R_SET : R_UNIFORM;
+}
+
+template <int N, int MODE>
+__host__ __device__ constexpr int role_idx(int p, int LF) {
+  const int r = free_rank<N, MODE>(p);
+  return r < LF ? r : r - LF;
+}
+
+template <int N, int NV, int LS, int MODE>
+struct Geo {
+  static constexpr int V = N * NV;
+  static constexpr int LV = V >= 11 ? 6 : (V > 5 ? V - 5 : 0);  // lane valuation bits
+  static constexpr int LF = 6 - LV;                              // lane frame bits
+  static constexpr int S = 1 << LS;                              // frame sets per lane
+  static constexpr int B = LF + LS;                              // log2 frames per block
+  static constexpr int CHB = V > 11 ? V - 11 : 0;                // valuation chunk bits
+  static constexpr int DS = LS == 0 ? 4 : 2;                     // stack slots
+};
+
+template <int N, int NV, int LS, int MODE>
+struct Ctx {
+  using G = Geo<N, NV, LS, MODE>;
+  uint32_t ru[N][N];                    // uniform relation words of the block
+  uint32_t lm[G::LF > 0 ? G::LF : 1];   // per-lane frame-bit words
+  uint32_t lv[G::LV > 0 ? G::LV : 1];   // per-lane valuation-bit words
+  uint32_t ch[G::CHB > 0 ? G::CHB : 1]; // uniform valuation-chunk words
+  uint32_t acc[G::S][N];
+  uint32_t stk[G::DS][G::S][N];
+};
+
+template <int N, int NV, int LS, int MODE>
+__device__ __forceinline__ uint32_t rel(const Ctx<N, NV, LS, MODE>& c, int s, int w, int v) {
+  using G = Geo<N, NV, LS, MODE>;
+  const int p = w * N + v;
+  const int ro = role<N, MODE, G::LF, LS>(p);
+  if (ro == R_ONE) return ~0u;
+  if (ro == R_LANE) return c.lm[role_idx<N, MODE>(p, 0)];
+  if (ro == R_SET) return ((s >> role_idx<N, MODE>(p, G::LF)) & 1) ? ~0u : 0u;
+  return c.ru[w][v];
+}
+
+template <int N, int NV, int LS, int MODE>
+__device__ __forceinline__ uint32_t var_word(const Ctx<N, NV, LS, MODE>& c, int i, int w) {
+  using G = Geo<N, NV, LS, MODE>;
+  const int b = i * N + w;
+  if (b < 5) return pattern(b);
+  if (b < 5 + G::LV) return c.lv[b - 5];
+  return c.ch[b - 5 - G::LV];
+}
+
+template <int N, int NV, int LS, int MODE, int L>
+__device__ __forceinline__ uint32_t leaf(const Ctx<N, NV, LS, MODE>& c, int s, int w) {
+  if constexpr (L < 4) {
+    return var_word(c, L, w);
+  } else if constexpr (L < 8) {
+    return ~var_word(c, L - 4, w);
+  } else if constexpr (L == L_SUCC || L == L_DEAD) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int v = 0; v < N; ++v) r |= rel(c, s, w, v);
+    return L == L_SUCC ? r : ~r;
+  } else if constexpr (L == L_TOP) {
+    return ~0u;
+  } else {
+    return 0u;
+  }
+}
+
+#define KR_FOR_SW                    \
+  _Pragma("unroll") for (int s = 0; s < Geo<N, NV, LS, MODE>::S; ++s) \
+  _Pragma("unroll") for (int w = 0; w < N; ++w)
+
+template <int N, int NV, int LS, int MODE, int L>
+__device__ __forceinline__ void f_load(Ctx<N, NV, LS, MODE>& c) {
+  KR_FOR_SW c.acc[s][w] = leaf<N, NV, LS, MODE, L>(c, s, w);
+}
+template <int N, int NV, int LS, int MODE, int L>
+__device__ __forceinline__ void f_and(Ctx<N, NV, LS, MODE>& c) {
+  KR_FOR_SW c.acc[s][w] &= leaf<N, NV, LS, MODE, L>(c, s, w);
+}
+template <int N, int NV, int LS, int MODE, int L>
+__device__ __forceinline__ void f_or(Ctx<N, NV, LS, MODE>& c) {
+  KR_FOR_SW c.acc[s][w] |= leaf<N, NV, LS, MODE, L>(c, s, w);
+}
+template <int N, int NV, int LS, int MODE, int L>
+__device__ __forceinline__ void f_iff(Ctx<N, NV, LS, MODE>& c) {
+  KR_FOR_SW c.acc[s][w] = ~(c.acc[s][w] ^ leaf<N, NV, LS, MODE, L>(c, s, w));
+}
+template <int N, int NV, int LS, int MODE, int D>
+__device__ __forceinline__ void f_save(Ctx<N, NV, LS, MODE>& c) {
+  if constexpr (D < Geo<N, NV, LS, MODE>::DS) {
+    KR_FOR_SW c.stk[D][s][w] = c.acc[s][w];
+  }
+}
+template <int N, int NV, int LS, int MODE, int D, int OP>
+__device__ __forceinline__ void f_comb(Ctx<N, NV, LS, MODE>& c) {
+  if constexpr (D < Geo<N, NV, LS, MODE>::DS) {
+    KR_FOR_SW {
+      if constexpr (OP == 0) c.acc[s][w] &= c.stk[D][s][w];
+      else if constexpr (OP == 1) c.acc[s][w] |= c.stk[D][s][w];
+      else c.acc[s][w] = ~(c.acc[s][w] ^ c.stk[D][s][w]);
+    }
+  }
+}
+// Truth table of a 3-input bitwise function for v_bitop3: bit (a*4 + b*2 + c)
+// of the immediate is f(a, b, c) for source operands (a, b, c).
+template <typename F>
+__host__ __device__ constexpr unsigned truth_table(F f) {
+  unsigned t = 0;
+  for (int i = 0; i < 8; ++i)
+    if (f((i >> 2) & 1, (i >> 1) & 1, i & 1)) t |= 1u << i;
+  return t;
+}
+constexpr unsigned kDiaTerm = truth_table([](int R, int t, int r) { return (R & t) | r; });
+constexpr unsigned kBoxTerm = truth_table([](int R, int t, int r) { return r & (t | !R); });
+
+// One (world w, successor v) term of Lemma 1: DIA accumulates R(w,v) & t_v
+// into an OR, BOX accumulates ~R(w,v) | t_v into an AND.  Relation words that
+// are compile-time constants (set bits, the reflexive diagonal) fold away.
+template <bool DIA, int N, int NV, int LS, int MODE>
+__device__ __forceinline__ uint32_t modal_term(const Ctx<N, NV, LS, MODE>& c, int s, int w, int v,
+                                               uint32_t t, uint32_t r) {
+  using G = Geo<N, NV, LS, MODE>;
+  const int p = w * N + v;
+  const int ro = role<N, MODE, G::LF, LS>(p);
+  if (ro == R_ONE || (ro == R_SET && ((s >> role_idx<N, MODE>(p, G::LF)) & 1)))
+    return DIA ? (r | t) : (r & t);
+  if (ro == R_SET) return r;
+  const uint32_t R = ro == R_LANE ? c.lm[role_idx<N, MODE>(p, 0)] : c.ru[w][v];
+  return __builtin_amdgcn_bitop3_b32(R, t, r, DIA ? kDiaTerm : kBoxTerm);
+}
+
+template <bool DIA, int N, int NV, int LS, int MODE>
+__device__ __forceinline__ void f_modal(Ctx<N, NV, LS, MODE>& c) {
+#pragma unroll
+  for (int s = 0; s < Geo<N, NV, LS, MODE>::S; ++s) {
+    uint32_t t[N];
+#pragma unroll
+    for (int w = 0; w < N; ++w) {
+      uint32_t r = DIA ? 0u : ~0u;
+#pragma unroll
+      for (int v = 0; v < N; ++v) r = modal_term<DIA>(c, s, w, v, c.acc[s][v], r);
+      t[w] = r;
+    }
+#pragma unroll
+    for (int w = 0; w < N; ++w) c.acc[s][w] = t[w];
+  }
+}
+
+#define KR_L10(BASE, FN)                                                               \
+  case BASE + 0: FN(0); break; case BASE + 1: FN(1); break; case BASE + 2: FN(2); break; \
+  case BASE + 3: FN(3); break; case BASE + 4: FN(4); break; case BASE + 5: FN(5); break; \
+  case BASE + 6: FN(6); break; case BASE + 7: FN(7); break; case BASE + 8: FN(8); break; \
+  case BASE + 9: FN(9); break;
+#define KR_D4(BASE, FN) \
+  case BASE + 0: FN(0); break; case BASE + 1: FN(1); break; case BASE + 2: FN(2); break; \
+  case BASE + 3: FN(3); break;
+
+template <int N, int NV, int LS, int MODE>
+__device__ __forceinline__ void run(Ctx<N, NV, LS, MODE>& c, const uint32_t* prog) {
+  uint32_t cur = 0;
+  for (int pc = 0;; ++pc) {
+    if ((pc & 3) == 0) cur = __builtin_amdgcn_readfirstlane(prog[pc >> 2]);
+    const uint32_t op = (cur >> ((pc & 3) * 8)) & 0xffu;
+    if (op == U_END) break;
+#define G_LOAD(L) f_load<N, NV, LS, MODE, L>(c)
+#define G_AND(L) f_and<N, NV, LS, MODE, L>(c)
+#define G_OR(L) f_or<N, NV, LS, MODE, L>(c)
+#define G_IFF(L) f_iff<N, NV, LS, MODE, L>(c)
+#define G_SAVE(D) f_save<N, NV, LS, MODE, D>(c)
+#define G_ANDS(D) f_comb<N, NV, LS, MODE, D, 0>(c)
+#define G_ORS(D) f_comb<N, NV, LS, MODE, D, 1>(c)
+#define G_IFFS(D) f_comb<N, NV, LS, MODE, D, 2>(c)
+    switch (op) {
+      KR_L10(U_LOAD, G_LOAD)
+      case U_LOAD + L_TOP: G_LOAD(L_TOP); break;
+      case U_LOAD + L_BOT: G_LOAD(L_BOT); break;
+      KR_L10(U_AND_L, G_AND)
+      KR_L10(U_OR_L, G_OR)
+      KR_L10(U_IFF_L, G_IFF)
+      case U_BOX: f_modal<false, N, NV, LS, MODE>(c); break;
+      case U_DIA: f_modal<true, N, NV, LS, MODE>(c); break;
+      KR_D4(U_SAVE, G_SAVE)
+      KR_D4(U_AND_S, G_ANDS)
+      KR_D4(U_OR_S, G_ORS)
+      KR_D4(U_IFF_S, G_IFFS)
+      default: break;
+    }
+#undef G_LOAD
+#undef G_AND
+#undef G_OR
+#undef G_IFF
+#undef G_SAVE
+#undef G_ANDS
+#undef G_ORS
+#undef G_IFFS
+  }
+}
+
+// Candidate key of the least failing model among the lanes' bits for one
+// (set, chunk) pass: the lowest failing lane holds the least frame and then
+// the least valuation, and the lowest failing bit its least in-word bits.
+template <int N, int NV, int LS, int MODE>
+__device__ __forceinline__ uint64_t candidate(const Ctx<N, NV, LS, MODE>& c, int s, uint32_t fail,
+                                              uint64_t bal, uint64_t blk, uint32_t chunk,
+                                              int lane) {
+  using G = Geo<N, NV, LS, MODE>;
+  const int fl = __builtin_ctzll(bal);
+  const uint32_t j = __builtin_ctz(fail | 0x80000000u);
+  uint32_t world = 0;
+#pragma unroll
+  for (int w = N - 1; w >= 0; --w)
+    if (!((c.acc[s][w] >> j) & 1u)) world = w;
+  const uint64_t pos = (blk << G::B) | ((uint64_t)s << G::LF) | (uint64_t)(lane >> G::LV);
+  const uint64_t frame = MODE == 0 ? pos : refl_frame(pos, N);
+  const uint64_t val = ((uint64_t)chunk << (5 + G::LV)) |
+                       ((uint64_t)(lane & ((1 << G::LV) - 1)) << 5) | j;
+  const uint64_t lk = (frame << (G::V + 4)) | (val << 4) | world;
+  return readlane64(lk, fl);
+}
+
+template <int N, int NV, int LS, int MODE, bool FUSED>
+__global__ __launch_bounds__(256) void census_fast(FastArgs a) {
+  using G = Geo<N, NV, LS, MODE>;
+  static_assert(G::V >= 5, "fast kernel needs n * nvars >= 5");
+  __shared__ uint32_t sprog[4][kMaxMicro / 4 + 4];
+  const int lane = threadIdx.x & 63;
+  uint32_t* prog = sprog[threadIdx.x >> 6];
+  constexpr int NC = FUSED ? 4 : 1;
+  const uint64_t blk_end = a.blk_begin + a.nblk;
+
+  Ctx<N, NV, LS, MODE> c;
+#pragma unroll
+  for (int i = 0; i < G::LF; ++i) c.lm[i] = 0u - ((lane >> (G::LV + i)) & 1u);
+#pragma unroll
+  for (int i = 0; i < G::LV; ++i) c.lv[i] = 0u - ((lane >> i) & 1u);
+  const uint32_t lane_pos = (uint32_t)(lane >> G::LV);
+
+  for (;;) {
+    uint64_t item = 0;
+    if (lane == 0) item = atomicAdd(a.queue, 1ull);
+    item = readlane64(item, 0);
+    if (item >= a.total_items) break;
+    const uint32_t f = a.order[item / a.items_per_formula];
+    const uint64_t b0 = a.blk_begin + (item % a.items_per_formula) * a.blocks_per_item;
+    const uint64_t b1 = b0 + a.blocks_per_item < blk_end ? b0 + a.blocks_per_item : blk_end;
+    unsigned long long* key_out = a.out_key + (uint64_t)f * a.out_stride;
+
+    if (a.decide) {
+      const uint64_t p0 = (b0 << G::B) > a.pos_begin ? (b0 << G::B) : a.pos_begin;
+      const uint64_t first_frame = MODE == 0 ? p0 : refl_frame(p0, N);
+      uint64_t known = __hip_atomic_load(key_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      known = readlane64(known, 0);
+      if (known != ~0ull && (known >> (G::V + 4)) < first_frame) continue;
+    }
+
+    const uint32_t p0 = a.uoff[f] >> 2, pw = (a.uoff[f + 1] >> 2) - p0;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.ucode) + p0;
+    for (uint32_t i = lane; i < pw; i += 64) prog[i] = src[i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    uint32_t cnt[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) cnt[k] = 0;
+    uint64_t key[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) key[k] = ~0ull;
+    bool done = false;
+
+    for (uint64_t blk = b0; blk < b1 && !done; ++blk) {
+      const uint64_t pbase = blk << G::B;
+      const uint64_t base = MODE == 0 ? pbase : refl_frame(pbase, N);
+#pragma unroll
+      for (int w = 0; w < N; ++w)
+#pragma unroll
+        for (int v = 0; v < N; ++v) {
+          const int p = w * N + v;
+          c.ru[w][v] = (uint32_t)__builtin_amdgcn_readfirstlane(
+              (int)(0u - (uint32_t)((base >> p) & 1u)));
+        }
+      // valid (lane, set) pairs: positions inside [pos_begin, pos_end)
+      const bool ragged = pbase < a.pos_begin || pbase + (1ull << G::B) > a.pos_end;
+      uint32_t lvl_word = 0;
+      if (FUSED) {
+        lvl_word = __builtin_amdgcn_readfirstlane(a.levels[pbase >> 4] >>
+                                                  ((uint32_t)(pbase & 15) * 2));
+      }
+      const bool classy = FUSED && (lvl_word & (G::B >= 4 ? 0xFFFFFFFFu
+                                                : ((1u << (2 << G::B)) - 1u))) != 0;
+      uint64_t best[NC];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) best[k] = ~0ull;
+
+      for (uint32_t chunk = 0; chunk < (1u << G::CHB); ++chunk) {
+#pragma unroll
+        for (int i = 0; i < G::CHB; ++i)
+          c.ch[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)(0u - ((chunk >> i) & 1u)));
+        run<N, NV, LS, MODE>(c, prog);
+#pragma unroll
+        for (int s = 0; s < G::S; ++s) {
+          uint32_t all = ~0u;
+#pragma unroll
+          for (int w = 0; w < N; ++w) all &= c.acc[s][w];
+          uint32_t fail = ~all;
+          if (ragged) {
+            const uint64_t pos = pbase | ((uint64_t)s << G::LF) | lane_pos;
+            if (pos < a.pos_begin || pos >= a.pos_end) fail = 0;
+          }
+          cnt[0] += __builtin_popcount(fail);
+          if (key[0] == ~0ull) {
+            const uint64_t bal = __ballot(fail != 0);
+            if (bal) {
+              const uint64_t k = candidate(c, s, fail, bal, blk, chunk, lane);
+              best[0] = k < best[0] ? k : best[0];
+            }
+          }
+          if constexpr (FUSED) {
+            if (classy) {
+              const uint32_t lvl = (lvl_word >> (2 * ((s << G::LF) | lane_pos))) & 3u;
+#pragma unroll
+              for (int k = 1; k < NC; ++k) {
+                const uint32_t fk = lvl >= (uint32_t)k ? fail : 0u;
+                cnt[k] += __builtin_popcount(fk);
+                if (key[k] == ~0ull) {
+                  const uint64_t bal = __ballot(fk != 0);
+                  if (bal) {
+                    const uint64_t kk = candidate(c, s, fk, bal, blk, chunk, lane);
+                    best[k] = kk < best[k] ? kk : best[k];
+                  }
+                }
+              }
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NC; ++k)
+        if (key[k] == ~0ull) key[k] = best[k];
+      if (a.decide && key[0] != ~0ull) done = true;
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      uint32_t ck = cnt[k];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) ck += __shfl_xor(ck, o);
+      if (lane == 0) {
+        if (key[k] != ~0ull) atomicMin(key_out + k * a.class_stride, (unsigned long long)key[k]);
+        if (ck && a.out_cnt)
+          atomicAdd(a.out_cnt + (uint64_t)f * a.out_stride + k * a.class_stride,
+                    (unsigned long long)ck);
+      }
+    }
+  }
+}
+
+// Class levels (0 K, 1 T, 2 S4, 3 S5), 2 bits per frame, 16 frames per word.
+__global__ void build_levels(int n, uint64_t nwords, uint32_t* levels) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nwords) return;
+  const uint32_t full = (1u << n) - 1u;
+  uint32_t word = 0;
+  for (int k = 0; k < 16; ++k) {
+    const uint64_t f = i * 16 + k;
+    if (f >> (n * n)) break;
+    uint32_t succ[8];
+    for (int w = 0; w < n; ++w) succ[w] = (uint32_t)(f >> (w * n)) & full;
+    int lvl = 3;
+    for (int w = 0; w < n && lvl; ++w)
+      if (!((succ[w] >> w) & 1u)) lvl = 0;
+    for (int w = 0; w < n && lvl > 1; ++w)
+      for (int v = 0; v < n; ++v)
+        if (((succ[w] >> v) & 1u) && (succ[v] & ~succ[w])) lvl = 1;
+    for (int w = 0; w < n && lvl > 2; ++w)
+      for (int v = 0; v < n; ++v)
+        if (((succ[w] >> v) & 1u) != ((succ[v] >> w) & 1u)) lvl = 2;
+    word |= (uint32_t)lvl << (2 * k);
+  }
+  levels[i] = word;
+}
+
+template <int N, int NV, int LS, int MODE, bool FUSED>
+hipError_t launch_t(const FastArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((census_fast<N, NV, LS, MODE, FUSED>), dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int N, int NV, int LS, int MODE, bool FUSED>
+int occ_t() {
+  int b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, census_fast<N, NV, LS, MODE, FUSED>, 256,
+                                                   0) != hipSuccess)
+    return 1;
+  return b > 0 ? b : 1;
+}
+
+struct Entry {
+  int n, nvars, ls, mode, fused;
+  hipError_t (*launch)(const FastArgs&, int, hipStream_t);
+  int (*occ)();
+};
+
+#define KR_E(N, NV, LS, MODE, F) {N, NV, LS, MODE, F, &launch_t<N, NV, LS, MODE, F>, &occ_t<N, NV, LS, MODE, F>}
+const Entry kTable[] = {
+    KR_E(5, 2, 0, 0, false), KR_E(5, 2, 1, 0, false), KR_E(5, 2, 2, 0, false),
+    KR_E(5, 2, 0, 0, true),  KR_E(5, 2, 1, 0, true),  KR_E(5, 2, 2, 0, true),
+    KR_E(5, 2, 0, 1, false), KR_E(5, 2, 1, 1, false), KR_E(5, 2, 2, 1, false),
+    KR_E(5, 3, 0, 0, false), KR_E(5, 3, 1, 0, false), KR_E(5, 3, 1, 1, false),
+    KR_E(5, 3, 1, 0, true),
+    KR_E(4, 3, 0, 0, false), KR_E(4, 3, 1, 0, false), KR_E(4, 3, 1, 1, false),
+    KR_E(4, 3, 1, 0, true),
+    KR_E(4, 2, 1, 0, false), KR_E(4, 2, 1, 1, false), KR_E(4, 2, 1, 0, true),
+    KR_E(6, 2, 0, 0, false), KR_E(6, 2, 1, 0, false), KR_E(6, 2, 1, 1, false),
+};
+
+const Entry* find(int n, int nvars, int ls, int mode, bool fused) {
+  for (const Entry& e : kTable)
+    if (e.n == n && e.nvars == nvars && e.ls == ls && e.mode == mode && e.fused == (int)fused)
+      return &e;
+  return nullptr;
+}
+
+}  // namespace
+
+bool fast_available(int n, int nvars, int ls, int mode, bool fused) {
+  return find(n, nvars, ls, mode, fused) != nullptr;
+}
+
+int fast_block_log2(int n, int nvars, int ls) {
+  const int V = n * nvars;
+  const int lv = V >= 11 ? 6 : (V > 5 ? V - 5 : 0);
+  return 6 - lv + ls;
+}
+
+hipError_t launch_fast(const FastArgs& a, int n, int nvars, int ls, int mode, bool fused, int grid,
+                       hipStream_t s) {
+  const Entry* e = find(n, nvars, ls, mode, fused);
+  if (!e) return hipErrorInvalidValue;
+  return e->launch(a, grid, s);
+}
+
+int fast_blocks_per_cu(int n, int nvars, int ls, int mode, bool fused) {
+  const Entry* e = find(n, nvars, ls, mode, fused);
+  return e ? e->occ() : 1;
+}
+
+hipError_t launch_levels(int n, uint32_t* levels, hipStream_t s) {
+  const uint64_t nwords = ((1ull << (n * n)) + 15) / 16;
+  hipLaunchKernelGGL(build_levels, dim3((uint32_t)((nwords + 255) / 256)), dim3(256), 0, s, n,
+                     nwords, levels);
+  return hipGetLastError();
+}
+
+uint64_t refl_frame_host(uint64_t j, int n) { return refl_frame(j, n); }
+
+}  // namespace kripke

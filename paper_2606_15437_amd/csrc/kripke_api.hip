@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -40,6 +41,7 @@ struct MicroBatch {
   std::vector<uint32_t> order;    // costliest first
   std::vector<int> is_const;
   uint64_t cost_total = 0;
+  int max_slots = 0;
 };
 
 int compile_batch(const uint8_t* code, const uint32_t* offsets, uint32_t count, uint32_t nvars,
@@ -73,6 +75,7 @@ int compile_batch(const uint8_t* code, const uint32_t* offsets, uint32_t count, 
     while (mb->code.size() % 4) mb->code.push_back(U_END);
     mb->off.push_back((uint32_t)mb->code.size());
     mb->is_const.push_back(c.is_const);
+    mb->max_slots = std::max(mb->max_slots, c.slots);
     cost[i] = (uint64_t)c.modal * n * n + (uint64_t)(c.binary + c.loads + c.saves) * n + 8;
     mb->cost_total += cost[i];
   }
@@ -100,6 +103,7 @@ struct ClassList {
 struct DeviceState {
   int cus = 0;
   std::map<std::pair<int, int>, ClassList> lists;  // (n, level)
+  std::map<int, uint32_t*> levels;                 // n -> 2-bit class level per frame
 };
 
 std::mutex g_mu;
@@ -150,6 +154,27 @@ int class_list(DeviceState* ds, int n, int level, const ClassList** out) {
   KR_HIP(hipStreamDestroy(s));
   auto res = ds->lists.emplace(key, std::move(cl));
   *out = &res.first->second;
+  return KRIPKE_OK;
+}
+
+// Class level of every frame on n <= 5 worlds, built once per device.
+int level_table(DeviceState* ds, int n, const uint32_t** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = ds->levels.find(n);
+  if (it != ds->levels.end()) {
+    *out = it->second;
+    return KRIPKE_OK;
+  }
+  const uint64_t nwords = ((1ull << (n * n)) + 15) / 16;
+  uint32_t* d = nullptr;
+  hipStream_t s;
+  KR_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  KR_HIP(hipMalloc(&d, nwords * sizeof(uint32_t)));
+  KR_HIP(launch_levels(n, d, s));
+  KR_HIP(hipStreamSynchronize(s));
+  KR_HIP(hipStreamDestroy(s));
+  ds->levels[n] = d;
+  *out = d;
   return KRIPKE_OK;
 }
 
@@ -275,6 +300,65 @@ int enqueue_scan(DeviceState* ds, const DeviceBatch& db, const Scan& sc, int n, 
   return KRIPKE_OK;
 }
 
+// Stack slots of the fast kernel variant with 2^ls frame sets per lane.
+int fast_slots(int ls) { return ls == 0 ? 4 : 2; }
+
+// Preferred number of frame sets per lane (log2) for the fast kernel, or -1
+// if no variant fits; KRIPKE_SETS_LOG2 overrides the default for tuning.
+int pick_sets(int n, int nvars, int mode, bool fused, int max_slots) {
+  static const char* env = getenv("KRIPKE_SETS_LOG2");
+  std::vector<int> pref = {1, 0, 2};
+  if (env) pref.insert(pref.begin(), atoi(env));
+  for (int ls : pref)
+    if (ls >= 0 && ls <= 2 && fast_available(n, nvars, ls, mode, fused) &&
+        max_slots <= fast_slots(ls))
+      return ls;
+  return -1;
+}
+
+// Enqueue the fast census over positions [p0, p1) (frame indices for mode 0,
+// reflexive ranks for mode 1).  With `fused`, out_key/out_cnt are the class-0
+// row of a [4][nformulas] result array.
+int enqueue_fast(DeviceState* ds, const DeviceBatch& db, int n, int nvars, int ls, int mode,
+                 bool fused, uint32_t nformulas, uint64_t p0, uint64_t p1,
+                 unsigned long long* key, unsigned long long* cnt, bool decide,
+                 unsigned long long* queue, hipStream_t s) {
+  FastArgs a{};
+  a.ucode = db.ucode;
+  a.uoff = db.uoff;
+  a.order = db.order;
+  a.nformulas = nformulas;
+  a.pos_begin = p0;
+  a.pos_end = p1;
+  const int B = fast_block_log2(n, nvars, ls);
+  a.blk_begin = p0 >> B;
+  a.nblk = p1 > p0 ? ((p1 + (1ull << B) - 1) >> B) - a.blk_begin : 0;
+  const int per_cu = fast_blocks_per_cu(n, nvars, ls, mode, fused);
+  const uint64_t waves = (uint64_t)ds->cus * per_cu * 4;
+  const uint64_t target = std::max<uint64_t>(16 * waves, nformulas);
+  uint64_t bpi = std::max<uint64_t>(1, (a.nblk * nformulas + target - 1) / target);
+  bpi = std::min<uint64_t>(bpi, 1ull << 16);
+  a.blocks_per_item = bpi;
+  a.items_per_formula = (a.nblk + bpi - 1) / bpi;
+  a.total_items = a.items_per_formula * nformulas;
+  a.queue = queue;
+  a.out_key = key;
+  a.out_cnt = cnt;
+  a.out_stride = 2;
+  a.class_stride = fused ? 2ull * nformulas : 0;
+  a.decide = decide;
+  if (fused) {
+    int rc = level_table(ds, n, &a.levels);
+    if (rc) return rc;
+  }
+  KR_HIP(launch_init(key, cnt, 2, fused ? 4 * nformulas : nformulas, queue, s));
+  if (a.nblk == 0) return KRIPKE_OK;
+  uint64_t grid = (uint64_t)ds->cus * per_cu;
+  grid = std::min<uint64_t>(grid, std::max<uint64_t>(1, (a.total_items + 3) / 4));
+  KR_HIP(launch_fast(a, n, nvars, ls, mode, fused, (int)grid, s));
+  return KRIPKE_OK;
+}
+
 }  // namespace
 
 // ================================================================= C ABI
@@ -314,14 +398,26 @@ int kripke_census_range(const uint8_t* code, const uint32_t* offsets, uint32_t n
   if ((rc = compile_batch(code, offsets, nformulas, nvars, (int)n, false, &mb))) return rc;
   DeviceState* ds = nullptr;
   if ((rc = device_state(&ds))) return rc;
-  Scan sc;
-  if ((rc = make_scan(ds, (int)n, (int)cls, frame_begin, frame_end, &sc))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  DeviceBatch db;
-  if ((rc = upload(mb, &db, 1, s))) return rc;
   auto* key = reinterpret_cast<unsigned long long*>(&d_out[0].first_key);
   auto* cnt = reinterpret_cast<unsigned long long*>(&d_out[0].fail_count);
-  rc = enqueue_scan(ds, db, sc, (int)n, (int)nvars, nformulas, key, cnt, 2, flags == KRIPKE_DECIDE,
+  const bool decide = flags == KRIPKE_DECIDE;
+  const int mode = cls == KRIPKE_K ? 0 : 1;
+  const int ls = cls <= KRIPKE_T ? pick_sets((int)n, (int)nvars, mode, false, mb.max_slots) : -1;
+  DeviceBatch db;
+  if (ls >= 0) {
+    const uint64_t p0 = mode == 0 ? frame_begin : t_rank(frame_begin, (int)n);
+    const uint64_t p1 = mode == 0 ? frame_end : t_rank(frame_end, (int)n);
+    if ((rc = upload(mb, &db, 1, s))) return rc;
+    rc = enqueue_fast(ds, db, (int)n, (int)nvars, ls, mode, false, nformulas, p0, p1, key, cnt,
+                      decide, db.queue, s);
+    int rc2 = release(&db, s);
+    return rc ? rc : rc2;
+  }
+  Scan sc;
+  if ((rc = make_scan(ds, (int)n, (int)cls, frame_begin, frame_end, &sc))) return rc;
+  if ((rc = upload(mb, &db, 1, s))) return rc;
+  rc = enqueue_scan(ds, db, sc, (int)n, (int)nvars, nformulas, key, cnt, 2, decide,
                     false, db.queue, s);
   int rc2 = release(&db, s);
   return rc ? rc : rc2;
@@ -417,6 +513,14 @@ int kripke_plan_create(const uint8_t* code, const uint32_t* offsets, uint32_t nf
         delete p;
         return rc;
       }
+  // tables used inside the captured graph must exist before capture
+  if (class_mask == 0xF && n <= 5 && pick_sets((int)n, (int)nvars, 0, true, p->mb.max_slots) >= 0) {
+    const uint32_t* lv = nullptr;
+    if ((rc = level_table(p->ds, (int)n, &lv))) {
+      delete p;
+      return rc;
+    }
+  }
   hipError_t e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete p;
@@ -432,9 +536,29 @@ int kripke_plan_create(const uint8_t* code, const uint32_t* offsets, uint32_t nf
 }
 
 static int plan_enqueue(KripkePlan* p, kripke_census_result* d_out, hipStream_t s) {
+  const int lsf = p->class_mask == 0xF && p->n <= 5
+                      ? pick_sets(p->n, p->nvars, 0, true, p->mb.max_slots) : -1;
+  if (lsf >= 0)  // one launch: every K frame reduces into each class containing it
+    return enqueue_fast(p->ds, p->db, p->n, p->nvars, lsf, 0, true, p->nformulas, 0,
+                        1ull << (p->n * p->n),
+                        reinterpret_cast<unsigned long long*>(&d_out[0].first_key),
+                        reinterpret_cast<unsigned long long*>(&d_out[0].fail_count), false,
+                        p->db.queue, s);
   for (int c = 0; c < 4; ++c) {
     if (!((p->class_mask >> c) & 1u)) continue;
     kripke_census_result* row = d_out + (size_t)c * p->nformulas;
+    const int mode = c == KRIPKE_K ? 0 : 1;
+    const int ls = c <= KRIPKE_T ? pick_sets(p->n, p->nvars, mode, false, p->mb.max_slots) : -1;
+    if (ls >= 0) {
+      const uint64_t nf = 1ull << (p->n * p->n);
+      int rc = enqueue_fast(p->ds, p->db, p->n, p->nvars, ls, mode, false, p->nformulas, 0,
+                            mode == 0 ? nf : t_rank(nf, p->n),
+                            reinterpret_cast<unsigned long long*>(&row[0].first_key),
+                            reinterpret_cast<unsigned long long*>(&row[0].fail_count), false,
+                            p->db.queue + c, s);
+      if (rc) return rc;
+      continue;
+    }
     int rc = enqueue_scan(p->ds, p->db, p->scans[c], p->n, p->nvars, p->nformulas,
                           reinterpret_cast<unsigned long long*>(&row[0].first_key),
                           reinterpret_cast<unsigned long long*>(&row[0].fail_count), 2, false,

@@ -229,6 +229,47 @@ def test_plan_graph_replay_matches_census(kr):
         kr.kripke_plan_destroy(plan)
 
 
+@pytest.mark.parametrize("n,nvars,getter,count", [(4, 3, "config2_formulas", 64),
+                                                  (5, 2, "config3_formulas", 48)])
+def test_fused_plan_matches_single_class(kr, n, nvars, getter, count):
+    """The one-launch all-class plan (every K frame reduced into each class containing it)
+    equals four single-class censuses, over several graph replays."""
+    import torch
+    fs = getattr(I, getter)()[:count]
+    code, offs = I.pack(fs)
+    out = torch.zeros((4, len(fs), 2), dtype=torch.int64, device="cuda")
+    plan = kr.kripke_plan_create(code, offs, n, 0xF, nvars)
+    try:
+        ref = {c: kr.census(fs, n, c, nvars) for c in CLASSES}
+        for rep in range(3):
+            out.fill_(-1)
+            kr.kripke_plan_launch(plan, out)
+            torch.cuda.synchronize()
+            r = kr.as_u64(out)
+            for c in CLASSES:
+                assert (r[c, :, 0] == ref[c][0]).all() and (r[c, :, 1] == ref[c][1]).all(), (rep, c)
+    finally:
+        kr.kripke_plan_destroy(plan)
+
+
+def test_fused_plan_small_classes_vs_oracle(kr, orc):
+    """Fused-plan S4 and S5 rows at n = 5 against the oracle directly."""
+    import torch
+    fs = I.config3_formulas()[100:116]
+    code, offs = I.pack(fs)
+    out = torch.zeros((4, len(fs), 2), dtype=torch.int64, device="cuda")
+    plan = kr.kripke_plan_create(code, offs, 5, 0xF, 2)
+    try:
+        kr.kripke_plan_launch(plan, out)
+        torch.cuda.synchronize()
+        r = kr.as_u64(out)
+    finally:
+        kr.kripke_plan_destroy(plan)
+    for c in (2, 3):
+        ek, ec = _oracle_all(orc, fs, 5, c, 2)
+        assert (r[c, :, 0] == ek).all() and (r[c, :, 1] == ec).all(), c
+
+
 # ------------------------------------------------------------- split
 @pytest.mark.parametrize("n", [6, 7, 8])
 def test_split_parity_families(kr, orc, n):
