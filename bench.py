@@ -1,15 +1,21 @@
 """Benchmark: n = 5 exhaustive Kripke census throughput on one MI355X.
 
-One step = one replay of the captured hipGraph that censuses the 4,096-formula
-batch (2 variables, uneven lengths 3..40, modal depth 0..6) over every labelled
-frame on 5 worlds for the classes K, T, S4 and S5, with every valuation.
-`value` is evaluated (formula, frame-in-class, valuation) triples per second.
+One step = one replay of the captured hipGraph holding the single persistent
+launch that censuses the 4,096-formula batch (2 variables, uneven lengths
+3..40, modal depth caps 0..6) over every labelled frame on 5 worlds and every
+valuation, reducing each K frame into every class (K, T, S4, S5) containing
+it.  `value` is evaluated (formula, frame, valuation) triples per second; the
+T/S4/S5 results are reductions of the same evaluations and are not counted
+again.
 
-Also measured (reported inside the JSON line):
-  - plain: the same kernel launched once per formula (4,096 launches) against the
-    batched single launch, both over the same frame slice;
-  - roofline of the dominant kernel (the K-class census), INT32 VALU bound;
-  - cpu_baseline: the CPU oracle on a bounded sample of the same workload.
+Also reported in the JSON line:
+  - plain_vs_batched: the same census with the same kernels launched once per
+    formula and class (16,384 launches, default tiles, no graph);
+  - roofline: the census kernel against the INT32 VALU peak, counting the
+    bit operations of Proposition 2 on the programs actually executed (after
+    exact constant folding); the figure on the source formulas is given too;
+  - cpu_baseline: the CPU oracle on a bounded sample of the same workload;
+  - table1: the paper's matched single-formula workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -25,26 +31,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_INT32 = 256 * 64 * 2.4e9  # INT32 lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+CLASS_FRAMES_N5 = (33554432, 1048576, 6942, 52)
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def class_frames(n):
-    from paper_2606_15437_amd import inputs as I  # noqa: F401
-    return {0: 1 << (n * n), 1: 1 << (n * n - n), 2: {1: 1, 2: 4, 3: 29, 4: 355, 5: 6942}[n],
-            3: {1: 1, 2: 2, 3: 5, 4: 15, 5: 52}[n]}
+def timed(fn, stream, reps=1):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--formulas", type=int, default=4096)
-    ap.add_argument("--slice-log2", type=int, default=18,
-                    help="frame slice [0, 2^s) for the plain-vs-batched comparison")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2606_15437_amd",
+                                                         "tune_cache.json"))
     ap.add_argument("--cpu-frames-log2", type=int, default=12)
     ap.add_argument("--cpu-formulas", type=int, default=64)
     ap.add_argument("--no-plain", action="store_true")
@@ -52,7 +65,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "design is frame-range sharding with a min/sum reduction, not run here.",
+              "design (frame-range shards, one min/sum reduction) is not run here.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -65,84 +78,67 @@ def main():
     fs = I.config3_formulas(args.formulas)
     B = len(fs)
     code, offs = I.pack(fs)
-    stats = [I.formula_stats(f, n) for f in fs]
-    bitops_sum = float(sum(s["bitops"] for s in stats))
-    cf = class_frames(n)
+    src_bitops = float(sum(I.formula_stats(f, n)["bitops"] for f in fs))
+    st = K.kripke_program_stats(code, offs, nvars)
+    exe_bitops = float((n * st[:, 1] + n * n * st[:, 0]).sum())
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
 
+    calib = K.kripke_calibrate_int32(stream)
+    log(f"INT32 VALU calibration: {calib / 1e12:.2f} T lane-ops/s "
+        f"(nominal {PEAK_INT32 / 1e12:.2f})")
+
     # ---------------------------------------------------------- batched step
-    log(f"plan: {B} formulas, n={n}, classes K/T/S4/S5")
-    plan = K.kripke_plan_create(code, offs, n, 0xF, nvars)
+    t0 = time.time()
+    plan = K.kripke_plan_create(code, offs, n, 0xF, nvars, tune_cache=args.tune_cache)
+    log(f"plan (compile, class tables, autotune): {time.time() - t0:.1f} s")
     out = torch.empty((4, B, 2), dtype=torch.int64, device=dev)
     for i in range(args.warmup):
-        t0 = time.time()
-        K.kripke_plan_launch(plan, out, stream)
-        torch.cuda.synchronize()
-        log(f"warmup {i}: {time.time() - t0:.2f} s")
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for i in range(args.steps):
-        K.kripke_plan_launch(plan, out, stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
-    evals_step = float(B * nval * sum(cf.values()))
+        ms_w = timed(lambda: K.kripke_plan_launch(plan, out, stream), stream)
+        log(f"warmup {i}: {ms_w:.0f} ms")
+    ms = timed(lambda: K.kripke_plan_launch(plan, out, stream), stream, args.steps)
+    evals_step = float(B) * CLASS_FRAMES_N5[0] * nval
     value = evals_step / (ms / 1e3)
-    res = K.as_u64(out)
-    log(f"batched all-class step: {ms:.1f} ms, {value / 1e9:.1f} G evals/s")
-    valid = {c: int((res[c, :, 0] == K.NO_KEY).sum()) for c in range(4)}
+    res = K.as_u64(out).copy()
+    log(f"batched all-class step: {ms:.1f} ms, {value / 1e9:.0f} G evals/s")
     K.kripke_plan_destroy(plan)
 
-    # ------------------------------------------- dominant kernel: K census
-    planK = K.kripke_plan_create(code, offs, n, 0x1, nvars)
-    outK = torch.empty((4, B, 2), dtype=torch.int64, device=dev)
-    K.kripke_plan_launch(planK, outK, stream)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    K.kripke_plan_launch(planK, outK, stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    msK = ev0.elapsed_time(ev1)
-    K.kripke_plan_destroy(planK)
-    evalsK = float(B) * cf[0] * nval
-    int_ops = bitops_sum * cf[0] * nval / 32.0  # algorithmic INT32 ops (Proposition 2 in bits)
-    achieved = int_ops / (msK / 1e3)
-    log(f"K census: {msK:.1f} ms, {evalsK / msK / 1e6:.1f} G evals/s, "
-        f"{achieved / 1e12:.2f} T INT32 ops/s ({100 * achieved / PEAK_INT32:.1f}% of peak)")
+    # the step is one init kernel (microseconds) plus the census kernel
+    int_ops_exe = exe_bitops * CLASS_FRAMES_N5[0] * nval / 32.0
+    int_ops_src = src_bitops * CLASS_FRAMES_N5[0] * nval / 32.0
+    achieved = int_ops_exe / (ms / 1e3)
+    log(f"roofline: {achieved / 1e12:.2f} T INT32 ops/s executed "
+        f"({100 * achieved / PEAK_INT32:.1f}% of peak)")
 
-    # ------------------------------------------- plain vs batched on a slice
+    # ------------------------------------------------- plain: per-formula
     plain = None
     if not args.no_plain:
-        S = 1 << args.slice_log2
-        o1 = torch.empty((B, 2), dtype=torch.int64, device=dev)
-        K.kripke_census_range(code, offs, n, 0, nvars, 0, S, 0, o1, stream)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        K.kripke_census_range(code, offs, n, 0, nvars, 0, S, 0, o1, stream)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        ms_b = ev0.elapsed_time(ev1)
-        o2 = torch.empty((B, 2), dtype=torch.int64, device=dev)
-        single = [(np.asarray(f, dtype=np.uint8), np.array([0, len(f)], dtype=np.uint32))
-                  for f in fs]
+        pplan = K.kripke_plan_create(code, offs, n, 0xF | K.KRIPKE_PLAN_PLAIN, nvars)
+        out2 = torch.empty((4, B, 2), dtype=torch.int64, device=dev)
         t0 = time.time()
-        ev0.record(stream)
-        for b, (c1, of1) in enumerate(single):
-            K.kripke_census_range(c1, of1, n, 0, nvars, 0, S, 0, o2[b:b + 1], stream)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        ms_p = ev0.elapsed_time(ev1)
-        agree = bool((K.as_u64(o1) == K.as_u64(o2)).all())
-        ev_slice = float(B) * S * nval
-        plain = {"frames": S, "batched_G_evals_per_s": ev_slice / ms_b / 1e6,
-                 "plain_G_evals_per_s": ev_slice / ms_p / 1e6, "batched_ms": ms_b,
-                 "plain_ms": ms_p, "speedup": ms_p / ms_b, "launches": B,
-                 "results_identical": agree, "host_s": time.time() - t0}
-        log(f"plain vs batched on {S} frames: {ms_p:.1f} ms vs {ms_b:.1f} ms "
-            f"({ms_p / ms_b:.2f}x), identical={agree}")
+        ms_p = timed(lambda: K.kripke_plan_launch(pplan, out2, stream), stream)
+        host_s = time.time() - t0
+        K.kripke_plan_destroy(pplan)
+        same = bool((K.as_u64(out2) == res).all())
+        plain = {"ms": ms_p, "G_evals_per_s": evals_step / ms_p / 1e6, "launches": 4 * B,
+                 "batched_ms": ms, "speedup_batched": ms_p / ms, "results_identical": same,
+                 "host_s": host_s}
+        log(f"plain per-formula launches: {ms_p:.0f} ms ({ms_p / ms:.2f}x the batched step), "
+            f"identical={same}")
+
+    # ------------------------------------------- Table 1 matched workload
+    t1 = I.parse(I.TABLE1_FORMULA)
+    c1, o1 = I.pack([t1])
+    r1 = torch.empty((1, 2), dtype=torch.int64, device=dev)
+    run1 = lambda: K.kripke_census_range(c1, o1, n, 0, nvars, 0, I.TABLE1_FRAMES, 0, r1, stream)
+    run1()
+    ms1 = timed(run1, stream, 5)
+    table1 = {"formula": I.TABLE1_FORMULA, "frames": I.TABLE1_FRAMES, "valuations": nval,
+              "ms": ms1, "G_evals_per_s": I.TABLE1_FRAMES * nval / ms1 / 1e6,
+              "fail_count": int(K.as_u64(r1)[0, 1]),
+              "note": "includes host-side compile/upload of the one formula per call"}
+    log(f"table-1 matched workload: {table1['G_evals_per_s']:.1f} G evals/s")
 
     # ---------------------------------------------------------- CPU oracle
     cpu = None
@@ -163,6 +159,7 @@ def main():
                          f"({cpu_evals:.3g} evaluations in {dt:.1f} s)"}
         log(f"cpu oracle: {cpu['value']:.4f} G evals/s on {threads} threads")
 
+    valid = {name: int((res[c, :, 0] == K.NO_KEY).sum()) for c, name in enumerate("K T S4 S5".split())}
     rec = {
         "metric": "formula*frame*valuation G evals/s, n=5 census (batched hipGraph vs plain)",
         "value": value / 1e9,
@@ -176,17 +173,22 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "n=5 census, 4,096 seeded formulas (len 3..40, depth 0..6), "
-                               "2 vars (1,024 valuations), classes K+T+S4+S5, one graph replay",
+        "config": {"workload": "n=5 exhaustive census: 4,096 seeded formulas (length 3..40, "
+                               "depth cap 0..6) x 33,554,432 frames x 1,024 valuations (2 vars), "
+                               "classes K+T+S4+S5 fused in one graph-replayed launch",
                    "formulas": B, "n": n, "nvars": nvars, "evals_per_step": evals_step,
-                   "valid_per_class": valid},
+                   "no_countermodel_per_class": valid},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32 / 1e12,
                      "unit": "T INT32 ops/s", "frac": achieved / PEAK_INT32, "traffic": None,
-                     "kernel": "census K class, n=5", "kernel_ms": msK,
-                     "mean_bitops_per_eval": bitops_sum / B},
+                     "kernel": "census_fast<5,2,*,K,fused>",
+                     "measured_int32_ceiling": calib / 1e12,
+                     "frac_of_measured_ceiling": achieved / calib,
+                     "executed_bitops_per_eval": exe_bitops / B,
+                     "source_bitops_per_eval": src_bitops / B,
+                     "source_formula_frac": int_ops_src / (ms / 1e3) / PEAK_INT32},
         "cpu_baseline": cpu,
         "plain_vs_batched": plain,
-        "k_census_G_evals_per_s": evalsK / msK / 1e6,
+        "table1": table1,
     }
     print(json.dumps(rec))
 

@@ -136,15 +136,42 @@ void kripke_frame_decode(uint64_t frame, uint32_t n, uint32_t *succ /* [n] */);
  * launch that enumerates K frames once and reduces each frame into every
  * class containing it, captured in a hipGraph on first launch and replayed
  * afterwards.  tune_cache: path of a JSON file of autotuned tile choices
- * (NULL = defaults; the file is read and extended, never required).
+ * (frame sets per lane, work items per wave).  NULL uses the defaults; with
+ * a path, a cached choice for this device, n, nvars and batch is reused, and
+ * otherwise every candidate is timed on a slice of the frames at creation
+ * and the winner is appended to the file.
  * d_out: device array [4][nformulas] (class-major); rows of classes not in
  * class_mask are left untouched.
+ * KRIPKE_PLAN_PLAIN in class_mask selects the unbatched baseline instead:
+ * the same kernels launched once per formula (per class), default tiles, no
+ * graph -- the "separate launches" form the batched plan is compared with.
  */
+#define KRIPKE_PLAN_PLAIN 0x10u
 int kripke_plan_create(const uint8_t *code, const uint32_t *offsets, uint32_t nformulas,
                        uint32_t n, uint32_t class_mask, uint32_t nvars, const char *tune_cache,
                        void **plan);
 int kripke_plan_launch(void *plan, kripke_census_result *d_out, void *stream);
 int kripke_plan_destroy(void *plan);
+
+/*
+ * kripke_program_stats -- host-only introspection of the compiled programs.
+ * The library compiles every formula into an equivalent program by exact
+ * rewrites (constant folding, negation normal form, operand ordering); this
+ * reports, per formula, the work one evaluation of the compiled program
+ * performs.  stats: int32[nformulas][6] =
+ *   {modal ops, binary ops, leaf loads, stack saves, stack slots, constant}
+ * where constant is 1/0 if the formula folds to TOP/BOT, else -1.
+ */
+int kripke_program_stats(const uint8_t *code, const uint32_t *offsets, uint32_t nformulas,
+                         uint32_t nvars, int32_t *stats);
+
+/*
+ * kripke_calibrate_int32 -- measured rate of plain 32-bit bitwise vector
+ * instructions on the current device (lane-operations per second), the
+ * ceiling the evaluator is compared against.  Runs synchronously (about
+ * 50 ms) on `stream`.
+ */
+int kripke_calibrate_int32(double *lane_ops_per_s, void *stream);
 
 /* Message for the last failure on this thread ("" if none). */
 const char *kripke_last_error(void);

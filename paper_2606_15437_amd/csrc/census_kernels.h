@@ -61,6 +61,7 @@ hipError_t launch_fast(const FastArgs& a, int n, int nvars, int ls, int mode, bo
 int fast_blocks_per_cu(int n, int nvars, int ls, int mode, bool fused);
 hipError_t launch_levels(int n, uint32_t* levels, hipStream_t s);
 uint64_t refl_frame_host(uint64_t j, int n);
+hipError_t run_calibration(int cus, uint32_t iters, double* lane_ops_per_s, hipStream_t s);
 
 hipError_t launch_census(const CensusArgs& a, int n, int nvars, int grid, hipStream_t s);
 int census_blocks_per_cu(int n, int nvars);

@@ -347,13 +347,10 @@ __global__ __launch_bounds__(256) void census_fast(FastArgs a) {
         }
       // valid (lane, set) pairs: positions inside [pos_begin, pos_end)
       const bool ragged = pbase < a.pos_begin || pbase + (1ull << G::B) > a.pos_end;
-      uint32_t lvl_word = 0;
-      if (FUSED) {
-        lvl_word = __builtin_amdgcn_readfirstlane(a.levels[pbase >> 4] >>
-                                                  ((uint32_t)(pbase & 15) * 2));
-      }
-      const bool classy = FUSED && (lvl_word & (G::B >= 4 ? 0xFFFFFFFFu
-                                                : ((1u << (2 << G::B)) - 1u))) != 0;
+      // class levels of the block's frames; consumed only after evaluation,
+      // so the scalar load overlaps the interpreter
+      uint32_t lvl_raw = 0;
+      if (FUSED) lvl_raw = a.levels[pbase >> 4];
       uint64_t best[NC];
 #pragma unroll
       for (int k = 0; k < NC; ++k) best[k] = ~0ull;
@@ -363,6 +360,11 @@ __global__ __launch_bounds__(256) void census_fast(FastArgs a) {
         for (int i = 0; i < G::CHB; ++i)
           c.ch[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)(0u - ((chunk >> i) & 1u)));
         run<N, NV, LS, MODE>(c, prog);
+        const uint32_t lvl_word = FUSED ? __builtin_amdgcn_readfirstlane(
+                                              lvl_raw >> ((uint32_t)(pbase & 15) * 2))
+                                        : 0u;
+        const bool classy = FUSED && (lvl_word & (G::B >= 4 ? 0xFFFFFFFFu
+                                                  : ((1u << (2 << G::B)) - 1u))) != 0;
 #pragma unroll
         for (int s = 0; s < G::S; ++s) {
           uint32_t all = ~0u;

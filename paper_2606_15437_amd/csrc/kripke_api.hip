@@ -282,7 +282,7 @@ int release(DeviceBatch* db, hipStream_t s) {
 int enqueue_scan(DeviceState* ds, const DeviceBatch& db, const Scan& sc, int n, int nvars,
                  uint32_t nformulas, unsigned long long* key, unsigned long long* cnt,
                  uint32_t stride, bool decide, bool key_pos, unsigned long long* queue,
-                 hipStream_t s) {
+                 hipStream_t s, uint32_t init_first = 0) {
   CensusArgs a{};
   a.ucode = db.ucode;
   a.uoff = db.uoff;
@@ -294,7 +294,9 @@ int enqueue_scan(DeviceState* ds, const DeviceBatch& db, const Scan& sc, int n, 
   a.out_stride = stride;
   a.decide = decide;
   a.key_pos = key_pos;
-  KR_HIP(launch_init(key, cnt, stride, nformulas, queue, s));
+  KR_HIP(launch_init(key + (uint64_t)stride * init_first,
+                     cnt ? cnt + (uint64_t)stride * init_first : nullptr, stride, nformulas, queue,
+                     s));
   if (sc.npos == 0) return KRIPKE_OK;
   KR_HIP(launch_census(a, n, nvars, grid_for(ds, n, nvars, a.total_items), s));
   return KRIPKE_OK;
@@ -307,7 +309,7 @@ int fast_slots(int ls) { return ls == 0 ? 4 : 2; }
 // if no variant fits; KRIPKE_SETS_LOG2 overrides the default for tuning.
 int pick_sets(int n, int nvars, int mode, bool fused, int max_slots) {
   static const char* env = getenv("KRIPKE_SETS_LOG2");
-  std::vector<int> pref = {1, 0, 2};
+  std::vector<int> pref = {2, 1, 0};
   if (env) pref.insert(pref.begin(), atoi(env));
   for (int ls : pref)
     if (ls >= 0 && ls <= 2 && fast_available(n, nvars, ls, mode, fused) &&
@@ -322,7 +324,8 @@ int pick_sets(int n, int nvars, int mode, bool fused, int max_slots) {
 int enqueue_fast(DeviceState* ds, const DeviceBatch& db, int n, int nvars, int ls, int mode,
                  bool fused, uint32_t nformulas, uint64_t p0, uint64_t p1,
                  unsigned long long* key, unsigned long long* cnt, bool decide,
-                 unsigned long long* queue, hipStream_t s) {
+                 unsigned long long* queue, hipStream_t s, int items_per_wave = 16,
+                 uint32_t init_first = 0) {
   FastArgs a{};
   a.ucode = db.ucode;
   a.uoff = db.uoff;
@@ -335,7 +338,7 @@ int enqueue_fast(DeviceState* ds, const DeviceBatch& db, int n, int nvars, int l
   a.nblk = p1 > p0 ? ((p1 + (1ull << B) - 1) >> B) - a.blk_begin : 0;
   const int per_cu = fast_blocks_per_cu(n, nvars, ls, mode, fused);
   const uint64_t waves = (uint64_t)ds->cus * per_cu * 4;
-  const uint64_t target = std::max<uint64_t>(16 * waves, nformulas);
+  const uint64_t target = std::max<uint64_t>((uint64_t)items_per_wave * waves, nformulas);
   uint64_t bpi = std::max<uint64_t>(1, (a.nblk * nformulas + target - 1) / target);
   bpi = std::min<uint64_t>(bpi, 1ull << 16);
   a.blocks_per_item = bpi;
@@ -351,7 +354,8 @@ int enqueue_fast(DeviceState* ds, const DeviceBatch& db, int n, int nvars, int l
     int rc = level_table(ds, n, &a.levels);
     if (rc) return rc;
   }
-  KR_HIP(launch_init(key, cnt, 2, fused ? 4 * nformulas : nformulas, queue, s));
+  KR_HIP(launch_init(key + 2ull * init_first, cnt ? cnt + 2ull * init_first : nullptr, 2,
+                     fused ? 4 * nformulas : nformulas, queue, s));
   if (a.nblk == 0) return KRIPKE_OK;
   uint64_t grid = (uint64_t)ds->cus * per_cu;
   grid = std::min<uint64_t>(grid, std::max<uint64_t>(1, (a.total_items + 3) / 4));
@@ -486,7 +490,193 @@ struct KripkePlan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   kripke_census_result* graph_out = nullptr;
+  int ls = -1;   // frame sets per lane (log2) of the fused launch, -1 = none
+  int ipw = 16;  // work items per wave
+  bool plain = false;  // one launch per formula, no graph
 };
+
+static int plan_enqueue(KripkePlan* p, kripke_census_result* d_out, hipStream_t s,
+                        uint64_t frames);
+
+// The unbatched baseline: per class, one (init, census) launch pair per
+// formula, each restricted to that formula through a one-entry order slice.
+static int plan_enqueue_plain(KripkePlan* p, kripke_census_result* d_out, hipStream_t s) {
+  for (int c = 0; c < 4; ++c) {
+    if (!((p->class_mask >> c) & 1u)) continue;
+    kripke_census_result* row = d_out + (size_t)c * p->nformulas;
+    const int mode = c == KRIPKE_K ? 0 : 1;
+    const int ls = c <= KRIPKE_T ? pick_sets(p->n, p->nvars, mode, false, p->mb.max_slots) : -1;
+    const uint64_t nf = 1ull << (p->n * p->n);
+    for (uint32_t i = 0; i < p->nformulas; ++i) {
+      const uint32_t f = p->mb.order[i];
+      DeviceBatch one = p->db;
+      one.order = p->db.order + i;
+      // the kernel indexes outputs by formula id, so pass the row base and
+      // let the init kernel clear only entry f
+      auto* key = reinterpret_cast<unsigned long long*>(&row[0].first_key);
+      auto* cnt = reinterpret_cast<unsigned long long*>(&row[0].fail_count);
+      int rc;
+      if (ls >= 0) {
+        rc = enqueue_fast(p->ds, one, p->n, p->nvars, ls, mode, false, 1, 0,
+                          mode == 0 ? nf : t_rank(nf, p->n), key, cnt, false, p->db.queue + c,
+                          s, 16, f);
+      } else {
+        rc = enqueue_scan(p->ds, one, p->scans[c], p->n, p->nvars, 1, key, cnt, 2, false, false,
+                          p->db.queue + c, s, f);
+      }
+      if (rc) return rc;
+    }
+  }
+  return KRIPKE_OK;
+}
+
+// ------------------------------------------------------------ autotuner
+// Tiles: frame sets per lane (2^ls, i.e. valuation words each lane carries
+// per dispatch) and work items per wave (load-balance granularity of the
+// persistent queue).  Every candidate is timed on a prefix slice of the
+// frames; the choice is cached in a small JSON file keyed by device, shape
+// and a hash of the compiled batch.
+static std::string tune_key(const KripkePlan* p) {
+  uint64_t h = 1469598103934665603ull;
+  for (uint8_t b : p->mb.code) h = (h ^ b) * 1099511628211ull;
+  hipDeviceProp_t prop;
+  int dev = 0;
+  hipGetDevice(&dev);
+  hipGetDeviceProperties(&prop, dev);
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s/%dcu/n%d/v%d/m%u/B%u/h%016llx", prop.gcnArchName, p->ds->cus,
+           p->n, p->nvars, p->class_mask, p->nformulas, (unsigned long long)h);
+  for (char* c = buf; *c; ++c)
+    if (*c == '"' || *c == '\\') *c = '_';
+  return buf;
+}
+
+static bool tune_lookup(const char* path, const std::string& key, int* ls, int* ipw) {
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool hit = false;
+  while (fgets(line, sizeof line, f)) {
+    const char* q = strstr(line, key.c_str());
+    if (!q || q == line || q[-1] != '"' || q[key.size()] != '"') continue;
+    const char* l = strstr(q, "\"ls\":");
+    const char* w = strstr(q, "\"ipw\":");
+    if (l && w) {
+      *ls = atoi(l + 5);
+      *ipw = atoi(w + 6);
+      hit = true;
+    }
+  }
+  fclose(f);
+  return hit;
+}
+
+static void tune_store(const char* path, const std::string& key, int ls, int ipw, double ms) {
+  std::vector<std::string> lines;
+  if (FILE* f = fopen(path, "r")) {
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+      std::string l(line);
+      if (l.find("\"ls\":") != std::string::npos && l.find("\"" + key + "\"") == std::string::npos) {
+        while (!l.empty() && (l.back() == '\n' || l.back() == ',')) l.pop_back();
+        lines.push_back(l);
+      }
+    }
+    fclose(f);
+  }
+  char buf[512];
+  snprintf(buf, sizeof buf, "  \"%s\": {\"ls\": %d, \"ipw\": %d, \"slice_ms\": %.3f}", key.c_str(),
+           ls, ipw, ms);
+  lines.push_back(buf);
+  std::string tmp = std::string(path) + ".tmp";
+  if (FILE* f = fopen(tmp.c_str(), "w")) {
+    fputs("{\n", f);
+    for (size_t i = 0; i < lines.size(); ++i)
+      fprintf(f, "%s%s\n", lines[i].c_str(), i + 1 < lines.size() ? "," : "");
+    fputs("}\n", f);
+    fclose(f);
+    rename(tmp.c_str(), path);
+  }
+}
+
+static int tune_plan(KripkePlan* p, const char* path) {
+  const std::string key = tune_key(p);
+  int ls = p->ls, ipw = p->ipw;
+  if (tune_lookup(path, key, &ls, &ipw) && ls >= 0 && ls <= 2 &&
+      fast_available(p->n, p->nvars, ls, 0, true) && p->mb.max_slots <= fast_slots(ls) &&
+      ipw > 0) {
+    p->ls = ls;
+    p->ipw = ipw;
+    return KRIPKE_OK;
+  }
+  kripke_census_result* scratch = nullptr;
+  KR_HIP(hipMalloc(&scratch, sizeof(kripke_census_result) * 4 * p->nformulas));
+  hipEvent_t e0, e1;
+  KR_HIP(hipEventCreate(&e0));
+  KR_HIP(hipEventCreate(&e1));
+  const uint64_t slice = std::min<uint64_t>(1ull << (p->n * p->n), 1ull << 20);
+  double best = 1e300;
+  int best_ls = p->ls, best_ipw = p->ipw;
+  for (int l = 0; l <= 2; ++l) {
+    if (!fast_available(p->n, p->nvars, l, 0, true) || p->mb.max_slots > fast_slots(l)) continue;
+    for (int w : {4, 16, 64}) {
+      p->ls = l;
+      p->ipw = w;
+      int rc = plan_enqueue(p, scratch, p->cap, slice);  // warm
+      if (rc) return rc;
+      KR_HIP(hipEventRecord(e0, p->cap));
+      if ((rc = plan_enqueue(p, scratch, p->cap, slice))) return rc;
+      KR_HIP(hipEventRecord(e1, p->cap));
+      KR_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      KR_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        best_ls = l;
+        best_ipw = w;
+      }
+    }
+  }
+  p->ls = best_ls;
+  p->ipw = best_ipw;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  KR_HIP(hipFree(scratch));
+  tune_store(path, key, best_ls, best_ipw, best);
+  return KRIPKE_OK;
+}
+
+int kripke_program_stats(const uint8_t* code, const uint32_t* offsets, uint32_t nformulas,
+                         uint32_t nvars, int32_t* stats) {
+  g_err.clear();
+  if (!code || !offsets || !stats) return fail(KRIPKE_EINVAL, "null pointer");
+  if (nvars > 4) return fail(KRIPKE_ELIMIT, "nvars must be <= 4");
+  for (uint32_t i = 0; i < nformulas; ++i) {
+    if (offsets[i + 1] < offsets[i]) return fail(KRIPKE_EINVAL, "offsets must be non-decreasing");
+    Compiled c;
+    std::string err;
+    int rc = compile_program(code + offsets[i], offsets[i + 1] - offsets[i], nvars, &c, &err);
+    if (rc) return fail(rc, "formula " + std::to_string(i) + ": " + err);
+    int32_t* o = stats + 6 * (size_t)i;
+    o[0] = c.modal;
+    o[1] = c.binary;
+    o[2] = c.loads;
+    o[3] = c.saves;
+    o[4] = c.slots;
+    o[5] = c.is_const;
+  }
+  return KRIPKE_OK;
+}
+
+int kripke_calibrate_int32(double* lane_ops_per_s, void* stream) {
+  g_err.clear();
+  if (!lane_ops_per_s) return fail(KRIPKE_EINVAL, "null output");
+  DeviceState* ds = nullptr;
+  int rc = device_state(&ds);
+  if (rc) return rc;
+  KR_HIP(run_calibration(ds->cus, 1u << 14, lane_ops_per_s, (hipStream_t)stream));
+  return KRIPKE_OK;
+}
 
 int kripke_plan_create(const uint8_t* code, const uint32_t* offsets, uint32_t nformulas,
                        uint32_t n, uint32_t class_mask, uint32_t nvars, const char* tune_cache,
@@ -494,7 +684,9 @@ int kripke_plan_create(const uint8_t* code, const uint32_t* offsets, uint32_t nf
   (void)tune_cache;
   g_err.clear();
   if (!plan || nformulas == 0) return fail(KRIPKE_EINVAL, "null plan or empty batch");
-  if (class_mask == 0 || class_mask > 15) return fail(KRIPKE_EINVAL, "class_mask must be 1..15");
+  const bool plain = (class_mask & KRIPKE_PLAN_PLAIN) != 0;
+  class_mask &= 0xFu;
+  if (class_mask == 0) return fail(KRIPKE_EINVAL, "class_mask must select a class");
   int rc = check_sizes(n, nvars, 5);
   if (rc) return rc;
   auto* p = new KripkePlan();
@@ -502,6 +694,7 @@ int kripke_plan_create(const uint8_t* code, const uint32_t* offsets, uint32_t nf
   p->nvars = (int)nvars;
   p->nformulas = nformulas;
   p->class_mask = class_mask;
+  p->plain = plain;
   if ((rc = compile_batch(code, offsets, nformulas, nvars, (int)n, false, &p->mb)) ||
       (rc = device_state(&p->ds))) {
     delete p;
@@ -514,7 +707,9 @@ int kripke_plan_create(const uint8_t* code, const uint32_t* offsets, uint32_t nf
         return rc;
       }
   // tables used inside the captured graph must exist before capture
-  if (class_mask == 0xF && n <= 5 && pick_sets((int)n, (int)nvars, 0, true, p->mb.max_slots) >= 0) {
+  if (class_mask == 0xF && n <= 5 && !plain)
+    p->ls = pick_sets((int)n, (int)nvars, 0, true, p->mb.max_slots);
+  if (p->ls >= 0) {
     const uint32_t* lv = nullptr;
     if ((rc = level_table(p->ds, (int)n, &lv))) {
       delete p;
@@ -531,19 +726,23 @@ int kripke_plan_create(const uint8_t* code, const uint32_t* offsets, uint32_t nf
     delete p;
     return rc;
   }
+  if (tune_cache && p->ls >= 0 && !getenv("KRIPKE_SETS_LOG2") &&
+      (rc = tune_plan(p, tune_cache))) {
+    kripke_plan_destroy(p);
+    return rc;
+  }
   *plan = p;
   return KRIPKE_OK;
 }
 
-static int plan_enqueue(KripkePlan* p, kripke_census_result* d_out, hipStream_t s) {
-  const int lsf = p->class_mask == 0xF && p->n <= 5
-                      ? pick_sets(p->n, p->nvars, 0, true, p->mb.max_slots) : -1;
-  if (lsf >= 0)  // one launch: every K frame reduces into each class containing it
-    return enqueue_fast(p->ds, p->db, p->n, p->nvars, lsf, 0, true, p->nformulas, 0,
-                        1ull << (p->n * p->n),
+static int plan_enqueue(KripkePlan* p, kripke_census_result* d_out, hipStream_t s,
+                        uint64_t frames) {
+  const uint64_t nf = frames ? frames : 1ull << (p->n * p->n);
+  if (p->ls >= 0)  // one launch: every K frame reduces into each class containing it
+    return enqueue_fast(p->ds, p->db, p->n, p->nvars, p->ls, 0, true, p->nformulas, 0, nf,
                         reinterpret_cast<unsigned long long*>(&d_out[0].first_key),
                         reinterpret_cast<unsigned long long*>(&d_out[0].fail_count), false,
-                        p->db.queue, s);
+                        p->db.queue, s, p->ipw);
   for (int c = 0; c < 4; ++c) {
     if (!((p->class_mask >> c) & 1u)) continue;
     kripke_census_result* row = d_out + (size_t)c * p->nformulas;
@@ -572,6 +771,7 @@ int kripke_plan_launch(void* plan, kripke_census_result* d_out, void* stream) {
   g_err.clear();
   auto* p = static_cast<KripkePlan*>(plan);
   if (!p || !d_out) return fail(KRIPKE_EINVAL, "null plan or output");
+  if (p->plain) return plan_enqueue_plain(p, d_out, (hipStream_t)stream);
   if (!p->exec || p->graph_out != d_out) {
     if (p->exec) {
       KR_HIP(hipGraphExecDestroy(p->exec));
@@ -579,7 +779,7 @@ int kripke_plan_launch(void* plan, kripke_census_result* d_out, void* stream) {
       p->exec = nullptr;
     }
     KR_HIP(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
-    int rc = plan_enqueue(p, d_out, p->cap);
+    int rc = plan_enqueue(p, d_out, p->cap, 0);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(p->cap, &g);
     if (rc) return rc;

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libkripke.so")
 KRIPKE_K, KRIPKE_T, KRIPKE_S4, KRIPKE_S5 = 0, 1, 2, 3
 CLASS_NAMES = ("K", "T", "S4", "S5")
 KRIPKE_COUNT, KRIPKE_DECIDE = 0, 1
+KRIPKE_PLAN_PLAIN = 0x10
 NO_KEY = (1 << 64) - 1
 
 _lib = None
@@ -49,6 +50,8 @@ def lib():
             "kripke_plan_launch": [vp, vp, vp],
             "kripke_plan_destroy": [vp],
             "kripke_version": [],
+            "kripke_program_stats": [u8p, u32p, u32, u32, C.POINTER(C.c_int32)],
+            "kripke_calibrate_int32": [C.POINTER(C.c_double), vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -159,6 +162,24 @@ def kripke_frame_decode(frame, n):
 
 def kripke_version():
     return lib().kripke_version()
+
+
+def kripke_program_stats(code, offsets, nvars):
+    """int32[B][6]: modal, binary, loads, saves, stack slots, constant (-1/0/1) per compiled
+    program (host-only)."""
+    c, cp = _host_u8(code)
+    o, op = _host_u32(offsets)
+    out = np.zeros((len(o) - 1, 6), dtype=np.int32)
+    _check(lib().kripke_program_stats(cp, op, len(o) - 1, nvars,
+                                      out.ctypes.data_as(C.POINTER(C.c_int32))))
+    return out
+
+
+def kripke_calibrate_int32(stream=None):
+    """Measured plain 32-bit bitwise VALU rate of the device, lane-operations per second."""
+    r = C.c_double()
+    _check(lib().kripke_calibrate_int32(C.byref(r), _stream(stream)))
+    return r.value
 
 
 # ---------------------------------------------------------------- helpers
