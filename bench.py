@@ -30,7 +30,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_INT32 = 256 * 64 * 2.4e9  # INT32 lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+# INT32 bitwise VALU peak: the published 157.3 TFLOP/s FP32 vector rate counts an FMA as
+# two flops, i.e. 256 CUs x 128 lanes/clk x 2.4 GHz = 78.6 T lane-operations/s.
+PEAK_INT32 = 256 * 128 * 2.4e9
 CLASS_FRAMES_N5 = (33554432, 1048576, 6942, 52)
 
 
@@ -58,7 +60,7 @@ def main():
     ap.add_argument("--formulas", type=int, default=4096)
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2606_15437_amd",
                                                          "tune_cache.json"))
-    ap.add_argument("--cpu-frames-log2", type=int, default=12)
+    ap.add_argument("--cpu-frames-log2", type=int, default=14)
     ap.add_argument("--cpu-formulas", type=int, default=64)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")

@@ -140,6 +140,15 @@ __device__ __forceinline__ void op_box(Regs<N, NV>& r) {
   for (int w = 0; w < N; ++w) r.acc[w] = t[w];
 }
 
+// DIA/BOX applied directly to a variable literal (a superinstruction).
+template <int N, int NV, bool DIA, int L>
+__device__ __forceinline__ void op_modal_leaf(Regs<N, NV>& r) {
+#pragma unroll
+  for (int v = 0; v < N; ++v) r.acc[v] = leaf_word<N, NV, L>(r, v);
+  if constexpr (DIA) op_dia<N, NV>(r);
+  else op_box<N, NV>(r);
+}
+
 template <int N, int NV, int D>
 __device__ __forceinline__ void op_save(Regs<N, NV>& r) {
 #pragma unroll
@@ -182,6 +191,8 @@ __device__ __forceinline__ void interpret(Regs<N, NV>& r, const uint32_t* prog) 
 #define F_ANDS(D) op_comb<N, NV, D, 0>(r)
 #define F_ORS(D) op_comb<N, NV, D, 1>(r)
 #define F_IFFS(D) op_comb<N, NV, D, 2>(r)
+#define F_DIAL(L) op_modal_leaf<N, NV, true, L>(r)
+#define F_BOXL(L) op_modal_leaf<N, NV, false, L>(r)
     switch (op) {
       KR_LEAF10(U_LOAD, F_LOAD)
       case U_LOAD + L_TOP: F_LOAD(L_TOP); break;
@@ -195,6 +206,12 @@ __device__ __forceinline__ void interpret(Regs<N, NV>& r, const uint32_t* prog) 
       KR_SLOT8(U_AND_S, F_ANDS)
       KR_SLOT8(U_OR_S, F_ORS)
       KR_SLOT8(U_IFF_S, F_IFFS)
+      KR_SLOT8(U_DIA_L, F_DIAL)
+      KR_SLOT8(U_BOX_L, F_BOXL)
+      case U_MM + 0: op_box<N, NV>(r); op_box<N, NV>(r); break;
+      case U_MM + 1: op_box<N, NV>(r); op_dia<N, NV>(r); break;
+      case U_MM + 2: op_dia<N, NV>(r); op_box<N, NV>(r); break;
+      case U_MM + 3: op_dia<N, NV>(r); op_dia<N, NV>(r); break;
       default: break;
     }
 #undef F_LOAD
@@ -205,6 +222,8 @@ __device__ __forceinline__ void interpret(Regs<N, NV>& r, const uint32_t* prog) 
 #undef F_ANDS
 #undef F_ORS
 #undef F_IFFS
+#undef F_DIAL
+#undef F_BOXL
   }
 }
 

@@ -79,13 +79,14 @@ struct Geo {
   static constexpr int S = 1 << LS;                              // frame sets per lane
   static constexpr int B = LF + LS;                              // log2 frames per block
   static constexpr int CHB = V > 11 ? V - 11 : 0;                // valuation chunk bits
-  static constexpr int DS = LS == 0 ? 4 : 2;                     // stack slots
+  static constexpr int DS = LS == 0 ? 4 : LS <= 2 ? 2 : 1;       // stack slots
 };
 
 template <int N, int NV, int LS, int MODE>
 struct Ctx {
   using G = Geo<N, NV, LS, MODE>;
   uint32_t ru[N][N];                    // uniform relation words of the block
+  uint32_t pv[5];                       // in-word valuation patterns, kept in VGPRs
   uint32_t lm[G::LF > 0 ? G::LF : 1];   // per-lane frame-bit words
   uint32_t lv[G::LV > 0 ? G::LV : 1];   // per-lane valuation-bit words
   uint32_t ch[G::CHB > 0 ? G::CHB : 1]; // uniform valuation-chunk words
@@ -108,7 +109,7 @@ template <int N, int NV, int LS, int MODE>
 __device__ __forceinline__ uint32_t var_word(const Ctx<N, NV, LS, MODE>& c, int i, int w) {
   using G = Geo<N, NV, LS, MODE>;
   const int b = i * N + w;
-  if (b < 5) return pattern(b);
+  if (b < 5) return c.pv[b];
   if (b < 5 + G::LV) return c.lv[b - 5];
   return c.ch[b - 5 - G::LV];
 }
@@ -131,26 +132,64 @@ __device__ __forceinline__ uint32_t leaf(const Ctx<N, NV, LS, MODE>& c, int s, i
   }
 }
 
+// Truth table of a 3-input bitwise function for v_bitop3: bit (a*4 + b*2 + c)
+// of the immediate is f(a, b, c) for source operands (a, b, c).
+template <typename F>
+__host__ __device__ constexpr unsigned truth_table(F f) {
+  unsigned t = 0;
+  for (int i = 0; i < 8; ++i)
+    if (f((i >> 2) & 1, (i >> 1) & 1, i & 1)) t |= 1u << i;
+  return t;
+}
+
+// Binary connective of the accumulator with a variable literal, the
+// literal's negation folded into the instruction: a loop-invariant ~x would
+// otherwise be hoisted out of the interpreter loop and held in registers.
+template <int OP, bool NEG>
+__device__ __forceinline__ uint32_t bin_lit(uint32_t a, uint32_t x) {
+  constexpr unsigned tt = truth_table([](int a, int x, int) {
+    const int y = NEG ? !x : x;
+    return OP == 0 ? (a & y) : OP == 1 ? (a | y) : (a == y);
+  });
+  return __builtin_amdgcn_bitop3_b32(a, x, x, tt);
+}
+
+__device__ __forceinline__ uint32_t opaque_not(uint32_t x) {
+  uint32_t r;
+  asm volatile("v_not_b32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
 #define KR_FOR_SW                    \
   _Pragma("unroll") for (int s = 0; s < Geo<N, NV, LS, MODE>::S; ++s) \
   _Pragma("unroll") for (int w = 0; w < N; ++w)
 
 template <int N, int NV, int LS, int MODE, int L>
 __device__ __forceinline__ void f_load(Ctx<N, NV, LS, MODE>& c) {
-  KR_FOR_SW c.acc[s][w] = leaf<N, NV, LS, MODE, L>(c, s, w);
+  if constexpr (L >= 4 && L < 8) {
+    KR_FOR_SW c.acc[s][w] = opaque_not(var_word(c, L - 4, w));
+  } else {
+    KR_FOR_SW c.acc[s][w] = leaf<N, NV, LS, MODE, L>(c, s, w);
+  }
+}
+template <int OP, int N, int NV, int LS, int MODE, int L>
+__device__ __forceinline__ void f_bin_leaf(Ctx<N, NV, LS, MODE>& c) {
+  if constexpr (L < 8) {
+    KR_FOR_SW c.acc[s][w] = bin_lit<OP, (L >= 4)>(c.acc[s][w], var_word(c, L & 3, w));
+  } else {
+    KR_FOR_SW {
+      const uint32_t y = leaf<N, NV, LS, MODE, L>(c, s, w);
+      c.acc[s][w] = OP == 0 ? (c.acc[s][w] & y) : OP == 1 ? (c.acc[s][w] | y)
+                                                          : ~(c.acc[s][w] ^ y);
+    }
+  }
 }
 template <int N, int NV, int LS, int MODE, int L>
-__device__ __forceinline__ void f_and(Ctx<N, NV, LS, MODE>& c) {
-  KR_FOR_SW c.acc[s][w] &= leaf<N, NV, LS, MODE, L>(c, s, w);
-}
+__device__ __forceinline__ void f_and(Ctx<N, NV, LS, MODE>& c) { f_bin_leaf<0, N, NV, LS, MODE, L>(c); }
 template <int N, int NV, int LS, int MODE, int L>
-__device__ __forceinline__ void f_or(Ctx<N, NV, LS, MODE>& c) {
-  KR_FOR_SW c.acc[s][w] |= leaf<N, NV, LS, MODE, L>(c, s, w);
-}
+__device__ __forceinline__ void f_or(Ctx<N, NV, LS, MODE>& c) { f_bin_leaf<1, N, NV, LS, MODE, L>(c); }
 template <int N, int NV, int LS, int MODE, int L>
-__device__ __forceinline__ void f_iff(Ctx<N, NV, LS, MODE>& c) {
-  KR_FOR_SW c.acc[s][w] = ~(c.acc[s][w] ^ leaf<N, NV, LS, MODE, L>(c, s, w));
-}
+__device__ __forceinline__ void f_iff(Ctx<N, NV, LS, MODE>& c) { f_bin_leaf<2, N, NV, LS, MODE, L>(c); }
 template <int N, int NV, int LS, int MODE, int D>
 __device__ __forceinline__ void f_save(Ctx<N, NV, LS, MODE>& c) {
   if constexpr (D < Geo<N, NV, LS, MODE>::DS) {
@@ -167,32 +206,31 @@ __device__ __forceinline__ void f_comb(Ctx<N, NV, LS, MODE>& c) {
     }
   }
 }
-// Truth table of a 3-input bitwise function for v_bitop3: bit (a*4 + b*2 + c)
-// of the immediate is f(a, b, c) for source operands (a, b, c).
-template <typename F>
-__host__ __device__ constexpr unsigned truth_table(F f) {
-  unsigned t = 0;
-  for (int i = 0; i < 8; ++i)
-    if (f((i >> 2) & 1, (i >> 1) & 1, i & 1)) t |= 1u << i;
-  return t;
-}
 constexpr unsigned kDiaTerm = truth_table([](int R, int t, int r) { return (R & t) | r; });
 constexpr unsigned kBoxTerm = truth_table([](int R, int t, int r) { return r & (t | !R); });
+constexpr unsigned kDiaTermN = truth_table([](int R, int t, int r) { return (R & !t) | r; });
+constexpr unsigned kBoxTermN = truth_table([](int R, int t, int r) { return r & (!t | !R); });
 
 // One (world w, successor v) term of Lemma 1: DIA accumulates R(w,v) & t_v
 // into an OR, BOX accumulates ~R(w,v) | t_v into an AND.  Relation words that
 // are compile-time constants (set bits, the reflexive diagonal) fold away.
-template <bool DIA, int N, int NV, int LS, int MODE>
+template <bool DIA, int N, int NV, int LS, int MODE, bool NEG = false>
 __device__ __forceinline__ uint32_t modal_term(const Ctx<N, NV, LS, MODE>& c, int s, int w, int v,
                                                uint32_t t, uint32_t r) {
   using G = Geo<N, NV, LS, MODE>;
   const int p = w * N + v;
   const int ro = role<N, MODE, G::LF, LS>(p);
-  if (ro == R_ONE || (ro == R_SET && ((s >> role_idx<N, MODE>(p, G::LF)) & 1)))
-    return DIA ? (r | t) : (r & t);
+  if (ro == R_ONE || (ro == R_SET && ((s >> role_idx<N, MODE>(p, G::LF)) & 1))) {
+    constexpr unsigned tt = truth_table([](int t, int r, int) {
+      const int u = NEG ? !t : t;
+      return DIA ? (r | u) : (r & u);
+    });
+    return __builtin_amdgcn_bitop3_b32(t, r, r, tt);
+  }
   if (ro == R_SET) return r;
   const uint32_t R = ro == R_LANE ? c.lm[role_idx<N, MODE>(p, 0)] : c.ru[w][v];
-  return __builtin_amdgcn_bitop3_b32(R, t, r, DIA ? kDiaTerm : kBoxTerm);
+  return __builtin_amdgcn_bitop3_b32(
+      R, t, r, DIA ? (NEG ? kDiaTermN : kDiaTerm) : (NEG ? kBoxTermN : kBoxTerm));
 }
 
 template <bool DIA, int N, int NV, int LS, int MODE>
@@ -212,22 +250,54 @@ __device__ __forceinline__ void f_modal(Ctx<N, NV, LS, MODE>& c) {
   }
 }
 
+// DIA/BOX applied directly to a literal: the literal's words are read in
+// place instead of being loaded into the accumulator first.
+template <bool DIA, int N, int NV, int LS, int MODE, int L>
+__device__ __forceinline__ void f_modal_leaf(Ctx<N, NV, LS, MODE>& c) {
+  static_assert(L < 8, "modal superinstructions take variable literals only");
+  // Every operand of this handler is invariant inside a block, so without an
+  // opaque seed the compiler would hoist all of these results out of the
+  // interpreter loop and keep them live in registers.
+  uint32_t seed;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(seed) : "i"(DIA ? 0 : -1));
+#pragma unroll
+  for (int s = 0; s < Geo<N, NV, LS, MODE>::S; ++s) {
+#pragma unroll
+    for (int w = 0; w < N; ++w) {
+      uint32_t r = seed;
+#pragma unroll
+      for (int v = 0; v < N; ++v)
+        r = modal_term<DIA, N, NV, LS, MODE, (L >= 4)>(c, s, w, v, var_word(c, L & 3, v), r);
+      c.acc[s][w] = r;
+    }
+  }
+}
+
 #define KR_L10(BASE, FN)                                                               \
   case BASE + 0: FN(0); break; case BASE + 1: FN(1); break; case BASE + 2: FN(2); break; \
   case BASE + 3: FN(3); break; case BASE + 4: FN(4); break; case BASE + 5: FN(5); break; \
   case BASE + 6: FN(6); break; case BASE + 7: FN(7); break; case BASE + 8: FN(8); break; \
   case BASE + 9: FN(9); break;
+#define KR_L8(BASE, FN)                                                                \
+  case BASE + 0: FN(0); break; case BASE + 1: FN(1); break; case BASE + 2: FN(2); break; \
+  case BASE + 3: FN(3); break; case BASE + 4: FN(4); break; case BASE + 5: FN(5); break; \
+  case BASE + 6: FN(6); break; case BASE + 7: FN(7); break;
 #define KR_D4(BASE, FN) \
   case BASE + 0: FN(0); break; case BASE + 1: FN(1); break; case BASE + 2: FN(2); break; \
   case BASE + 3: FN(3); break;
 
+// Interpret the wave's program (staged in LDS, 8-byte padded) on the current
+// block.  Ops are consumed from a 64-bit shift register holding the next
+// eight; a zero byte means either the end of the program or an exhausted
+// register, told apart by the number of 8-byte words left.
 template <int N, int NV, int LS, int MODE>
-__device__ __forceinline__ void run(Ctx<N, NV, LS, MODE>& c, const uint32_t* prog) {
-  uint32_t cur = 0;
-  for (int pc = 0;; ++pc) {
-    if ((pc & 3) == 0) cur = __builtin_amdgcn_readfirstlane(prog[pc >> 2]);
-    const uint32_t op = (cur >> ((pc & 3) * 8)) & 0xffu;
-    if (op == U_END) break;
+__device__ __forceinline__ void run(Ctx<N, NV, LS, MODE>& c, const uint32_t* prog, uint64_t first,
+                                    uint32_t nwords) {
+  uint64_t cur = first;
+  uint32_t next = 1;
+  for (;;) {
+    const uint32_t op = (uint32_t)cur & 0xffu;
+    cur >>= 8;
 #define G_LOAD(L) f_load<N, NV, LS, MODE, L>(c)
 #define G_AND(L) f_and<N, NV, LS, MODE, L>(c)
 #define G_OR(L) f_or<N, NV, LS, MODE, L>(c)
@@ -236,7 +306,16 @@ __device__ __forceinline__ void run(Ctx<N, NV, LS, MODE>& c, const uint32_t* pro
 #define G_ANDS(D) f_comb<N, NV, LS, MODE, D, 0>(c)
 #define G_ORS(D) f_comb<N, NV, LS, MODE, D, 1>(c)
 #define G_IFFS(D) f_comb<N, NV, LS, MODE, D, 2>(c)
+#define G_DIAL(L) f_modal_leaf<true, N, NV, LS, MODE, L>(c)
+#define G_BOXL(L) f_modal_leaf<false, N, NV, LS, MODE, L>(c)
     switch (op) {
+      case U_END:
+        if (next >= nwords) return;
+        cur = ((uint64_t)__builtin_amdgcn_readfirstlane(prog[2 * next + 1]) << 32) |
+              __builtin_amdgcn_readfirstlane(prog[2 * next]);
+        ++next;
+        if ((cur & 0xffu) == 0) return;
+        break;
       KR_L10(U_LOAD, G_LOAD)
       case U_LOAD + L_TOP: G_LOAD(L_TOP); break;
       case U_LOAD + L_BOT: G_LOAD(L_BOT); break;
@@ -249,7 +328,13 @@ __device__ __forceinline__ void run(Ctx<N, NV, LS, MODE>& c, const uint32_t* pro
       KR_D4(U_AND_S, G_ANDS)
       KR_D4(U_OR_S, G_ORS)
       KR_D4(U_IFF_S, G_IFFS)
-      default: break;
+      KR_L8(U_DIA_L, G_DIAL)
+      KR_L8(U_BOX_L, G_BOXL)
+      case U_MM + 0: f_modal<false, N, NV, LS, MODE>(c); f_modal<false, N, NV, LS, MODE>(c); break;
+      case U_MM + 1: f_modal<false, N, NV, LS, MODE>(c); f_modal<true, N, NV, LS, MODE>(c); break;
+      case U_MM + 2: f_modal<true, N, NV, LS, MODE>(c); f_modal<false, N, NV, LS, MODE>(c); break;
+      case U_MM + 3: f_modal<true, N, NV, LS, MODE>(c); f_modal<true, N, NV, LS, MODE>(c); break;
+      default: __builtin_unreachable();
     }
 #undef G_LOAD
 #undef G_AND
@@ -259,6 +344,8 @@ __device__ __forceinline__ void run(Ctx<N, NV, LS, MODE>& c, const uint32_t* pro
 #undef G_ANDS
 #undef G_ORS
 #undef G_IFFS
+#undef G_DIAL
+#undef G_BOXL
   }
 }
 
@@ -295,6 +382,15 @@ __global__ __launch_bounds__(256) void census_fast(FastArgs a) {
   const uint64_t blk_end = a.blk_begin + a.nblk;
 
   Ctx<N, NV, LS, MODE> c;
+  // Patterns live in vector registers on purpose: a modal term combines a
+  // scalar relation word with a pattern, and an instruction takes at most one
+  // scalar operand.
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    uint32_t v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(pattern(b)));
+    c.pv[b] = v;
+  }
 #pragma unroll
   for (int i = 0; i < G::LF; ++i) c.lm[i] = 0u - ((lane >> (G::LV + i)) & 1u);
 #pragma unroll
@@ -325,6 +421,12 @@ __global__ __launch_bounds__(256) void census_fast(FastArgs a) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint64_t first = ((uint64_t)__builtin_amdgcn_readfirstlane(prog[1]) << 32) |
+                           __builtin_amdgcn_readfirstlane(prog[0]);
+    // TOP holds everywhere: no countermodel, nothing to scan.  BOT fails at
+    // world 0 of every model: every block is all-fail without interpretation.
+    if (first == (uint64_t)(U_LOAD + L_TOP)) continue;
+    const bool all_fail = first == (uint64_t)(U_LOAD + L_BOT);
 
     uint32_t cnt[NC];
 #pragma unroll
@@ -342,8 +444,11 @@ __global__ __launch_bounds__(256) void census_fast(FastArgs a) {
 #pragma unroll
         for (int v = 0; v < N; ++v) {
           const int p = w * N + v;
-          c.ru[w][v] = (uint32_t)__builtin_amdgcn_readfirstlane(
-              (int)(0u - (uint32_t)((base >> p) & 1u)));
+          if (role<N, MODE, G::LF, LS>(p) != R_UNIFORM) continue;
+          if (N * N <= 32)  // one scalar signed bit-field extract per word
+            c.ru[w][v] = (uint32_t)__builtin_amdgcn_sbfe((int)(uint32_t)base, p, 1);
+          else
+            c.ru[w][v] = 0u - (uint32_t)((base >> p) & 1u);
         }
       // valid (lane, set) pairs: positions inside [pos_begin, pos_end)
       const bool ragged = pbase < a.pos_begin || pbase + (1ull << G::B) > a.pos_end;
@@ -359,7 +464,14 @@ __global__ __launch_bounds__(256) void census_fast(FastArgs a) {
 #pragma unroll
         for (int i = 0; i < G::CHB; ++i)
           c.ch[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)(0u - ((chunk >> i) & 1u)));
-        run<N, NV, LS, MODE>(c, prog);
+        if (all_fail) {
+#pragma unroll
+          for (int ss = 0; ss < G::S; ++ss)
+#pragma unroll
+            for (int w = 0; w < N; ++w) c.acc[ss][w] = 0u;
+        } else {
+          run<N, NV, LS, MODE>(c, prog, first, pw >> 1);
+        }
         const uint32_t lvl_word = FUSED ? __builtin_amdgcn_readfirstlane(
                                               lvl_raw >> ((uint32_t)(pbase & 15) * 2))
                                         : 0u;
@@ -472,6 +584,7 @@ struct Entry {
 const Entry kTable[] = {
     KR_E(5, 2, 0, 0, false), KR_E(5, 2, 1, 0, false), KR_E(5, 2, 2, 0, false),
     KR_E(5, 2, 0, 0, true),  KR_E(5, 2, 1, 0, true),  KR_E(5, 2, 2, 0, true),
+    KR_E(5, 2, 3, 0, false), KR_E(5, 2, 3, 0, true),  KR_E(5, 2, 3, 1, false),
     KR_E(5, 2, 0, 1, false), KR_E(5, 2, 1, 1, false), KR_E(5, 2, 2, 1, false),
     KR_E(5, 3, 0, 0, false), KR_E(5, 3, 1, 0, false), KR_E(5, 3, 1, 1, false),
     KR_E(5, 3, 1, 0, true),

@@ -42,6 +42,7 @@ struct MicroBatch {
   std::vector<int> is_const;
   uint64_t cost_total = 0;
   int max_slots = 0;
+  std::vector<int> slots;         // stack slots per formula
 };
 
 int compile_batch(const uint8_t* code, const uint32_t* offsets, uint32_t count, uint32_t nvars,
@@ -54,6 +55,8 @@ int compile_batch(const uint8_t* code, const uint32_t* offsets, uint32_t count, 
   mb->code.clear();
   mb->off.assign(1, 0);
   mb->is_const.clear();
+  mb->slots.clear();
+  mb->max_slots = 0;
   std::vector<uint64_t> cost(count);
   for (uint32_t i = 0; i < count; ++i) {
     Compiled c;
@@ -72,10 +75,11 @@ int compile_batch(const uint8_t* code, const uint32_t* offsets, uint32_t count, 
       return fail(KRIPKE_ELIMIT, (pairs ? "pair " : "formula ") + std::to_string(i) +
                                      ": compiled program too long");
     mb->code.insert(mb->code.end(), c.micro.begin(), c.micro.end());
-    while (mb->code.size() % 4) mb->code.push_back(U_END);
+    while (mb->code.size() % 8) mb->code.push_back(U_END);  // kernels fetch 8 ops at a time
     mb->off.push_back((uint32_t)mb->code.size());
     mb->is_const.push_back(c.is_const);
     mb->max_slots = std::max(mb->max_slots, c.slots);
+    mb->slots.push_back(c.slots);
     cost[i] = (uint64_t)c.modal * n * n + (uint64_t)(c.binary + c.loads + c.saves) * n + 8;
     mb->cost_total += cost[i];
   }
@@ -303,7 +307,7 @@ int enqueue_scan(DeviceState* ds, const DeviceBatch& db, const Scan& sc, int n, 
 }
 
 // Stack slots of the fast kernel variant with 2^ls frame sets per lane.
-int fast_slots(int ls) { return ls == 0 ? 4 : 2; }
+int fast_slots(int ls) { return ls == 0 ? 4 : ls <= 2 ? 2 : 1; }
 
 // Preferred number of frame sets per lane (log2) for the fast kernel, or -1
 // if no variant fits; KRIPKE_SETS_LOG2 overrides the default for tuning.
@@ -312,10 +316,53 @@ int pick_sets(int n, int nvars, int mode, bool fused, int max_slots) {
   std::vector<int> pref = {2, 1, 0};
   if (env) pref.insert(pref.begin(), atoi(env));
   for (int ls : pref)
-    if (ls >= 0 && ls <= 2 && fast_available(n, nvars, ls, mode, fused) &&
+    if (ls >= 0 && ls <= 3 && fast_available(n, nvars, ls, mode, fused) &&
         max_slots <= fast_slots(ls))
       return ls;
   return -1;
+}
+
+// Two-tier split of a batch for the fast kernel: programs whose stack need
+// fits variant `ls` run in one launch, the deeper rest in a second launch
+// with the widest variant that fits them.  order = tier A then tier B, each
+// costliest first.
+struct Tiering {
+  std::vector<uint32_t> order;
+  uint32_t count_a = 0;
+  int ls_a = -1, ls_b = -1;
+};
+
+bool make_tiers(const MicroBatch& mb, int n, int nvars, int mode, bool fused, int ls,
+                Tiering* t) {
+  if (ls < 0 || !fast_available(n, nvars, ls, mode, fused)) return false;
+  t->order.clear();
+  int max_b = 0;
+  for (uint32_t f : mb.order)
+    if (mb.slots[f] <= fast_slots(ls)) t->order.push_back(f);
+  t->count_a = (uint32_t)t->order.size();
+  for (uint32_t f : mb.order)
+    if (mb.slots[f] > fast_slots(ls)) {
+      t->order.push_back(f);
+      max_b = std::max(max_b, mb.slots[f]);
+    }
+  t->ls_a = ls;
+  t->ls_b = -1;
+  if (t->count_a < t->order.size()) {
+    for (int l = 2; l >= 0 && t->ls_b < 0; --l)
+      if (fast_available(n, nvars, l, mode, fused) && max_b <= fast_slots(l)) t->ls_b = l;
+    if (t->ls_b < 0) return false;
+  }
+  return true;
+}
+
+// Preferred tiering for a batch (env override, then widest variant first).
+bool pick_tiers(const MicroBatch& mb, int n, int nvars, int mode, bool fused, Tiering* t) {
+  static const char* env = getenv("KRIPKE_SETS_LOG2");
+  std::vector<int> pref = {2, 1, 3, 0};
+  if (env) pref.insert(pref.begin(), atoi(env));
+  for (int ls : pref)
+    if (ls >= 0 && ls <= 3 && make_tiers(mb, n, nvars, mode, fused, ls, t)) return true;
+  return false;
 }
 
 // Enqueue the fast census over positions [p0, p1) (frame indices for mode 0,
@@ -325,11 +372,15 @@ int enqueue_fast(DeviceState* ds, const DeviceBatch& db, int n, int nvars, int l
                  bool fused, uint32_t nformulas, uint64_t p0, uint64_t p1,
                  unsigned long long* key, unsigned long long* cnt, bool decide,
                  unsigned long long* queue, hipStream_t s, int items_per_wave = 16,
-                 uint32_t init_first = 0) {
+                 uint32_t init_first = 0, uint32_t order_first = 0, bool init = true,
+                 uint32_t row_formulas = 0) {
+  // row_formulas: formulas per class row of the output (the whole batch, which
+  // a tier launch covers only part of)
+  if (row_formulas == 0) row_formulas = nformulas;
   FastArgs a{};
   a.ucode = db.ucode;
   a.uoff = db.uoff;
-  a.order = db.order;
+  a.order = db.order + order_first;
   a.nformulas = nformulas;
   a.pos_begin = p0;
   a.pos_end = p1;
@@ -348,18 +399,42 @@ int enqueue_fast(DeviceState* ds, const DeviceBatch& db, int n, int nvars, int l
   a.out_key = key;
   a.out_cnt = cnt;
   a.out_stride = 2;
-  a.class_stride = fused ? 2ull * nformulas : 0;
+  a.class_stride = fused ? 2ull * row_formulas : 0;
   a.decide = decide;
   if (fused) {
     int rc = level_table(ds, n, &a.levels);
     if (rc) return rc;
   }
-  KR_HIP(launch_init(key + 2ull * init_first, cnt ? cnt + 2ull * init_first : nullptr, 2,
-                     fused ? 4 * nformulas : nformulas, queue, s));
-  if (a.nblk == 0) return KRIPKE_OK;
+  if (init)
+    KR_HIP(launch_init(key + 2ull * init_first, cnt ? cnt + 2ull * init_first : nullptr, 2,
+                       fused ? 4 * nformulas : nformulas, queue, s));
+  else
+    KR_HIP(launch_init(nullptr, nullptr, 2, 0, queue, s));
+  if (a.nblk == 0 || nformulas == 0) return KRIPKE_OK;
   uint64_t grid = (uint64_t)ds->cus * per_cu;
   grid = std::min<uint64_t>(grid, std::max<uint64_t>(1, (a.total_items + 3) / 4));
   KR_HIP(launch_fast(a, n, nvars, ls, mode, fused, (int)grid, s));
+  return KRIPKE_OK;
+}
+
+// Enqueue a tiered fast census: one init, then one launch per tier.  The
+// device order array must already hold t.order.
+int enqueue_tiered(DeviceState* ds, const DeviceBatch& db, const Tiering& t, int n, int nvars,
+                   int mode, bool fused, uint32_t nformulas, uint64_t p0, uint64_t p1,
+                   unsigned long long* key, unsigned long long* cnt, bool decide,
+                   unsigned long long* queues, hipStream_t s, int ipw) {
+  KR_HIP(launch_init(key, cnt, 2, fused ? 4 * nformulas : nformulas, nullptr, s));
+  int rc = enqueue_fast(ds, db, n, nvars, t.ls_a, mode, fused, t.count_a, p0, p1, key, cnt, decide,
+                        queues, s, ipw, 0, 0, false, nformulas);
+  if (rc || t.count_a == (uint32_t)t.order.size()) return rc;
+  return enqueue_fast(ds, db, n, nvars, t.ls_b, mode, fused,
+                      (uint32_t)t.order.size() - t.count_a, p0, p1, key, cnt, decide, queues + 1,
+                      s, ipw, 0, t.count_a, false, nformulas);
+}
+
+int upload_order(const Tiering& t, uint32_t* d_order, hipStream_t s) {
+  KR_HIP(hipMemcpyAsync(d_order, t.order.data(), t.order.size() * 4, hipMemcpyHostToDevice, s));
+  KR_HIP(hipStreamSynchronize(s));
   return KRIPKE_OK;
 }
 
@@ -407,14 +482,15 @@ int kripke_census_range(const uint8_t* code, const uint32_t* offsets, uint32_t n
   auto* cnt = reinterpret_cast<unsigned long long*>(&d_out[0].fail_count);
   const bool decide = flags == KRIPKE_DECIDE;
   const int mode = cls == KRIPKE_K ? 0 : 1;
-  const int ls = cls <= KRIPKE_T ? pick_sets((int)n, (int)nvars, mode, false, mb.max_slots) : -1;
+  Tiering tiers;
   DeviceBatch db;
-  if (ls >= 0) {
+  if (cls <= KRIPKE_T && pick_tiers(mb, (int)n, (int)nvars, mode, false, &tiers)) {
     const uint64_t p0 = mode == 0 ? frame_begin : t_rank(frame_begin, (int)n);
     const uint64_t p1 = mode == 0 ? frame_end : t_rank(frame_end, (int)n);
-    if ((rc = upload(mb, &db, 1, s))) return rc;
-    rc = enqueue_fast(ds, db, (int)n, (int)nvars, ls, mode, false, nformulas, p0, p1, key, cnt,
-                      decide, db.queue, s);
+    if ((rc = upload(mb, &db, 2, s))) return rc;
+    if ((rc = upload_order(tiers, db.order, s))) return rc;
+    rc = enqueue_tiered(ds, db, tiers, (int)n, (int)nvars, mode, false, nformulas, p0, p1, key,
+                        cnt, decide, db.queue, s, 16);
     int rc2 = release(&db, s);
     return rc ? rc : rc2;
   }
@@ -492,6 +568,7 @@ struct KripkePlan {
   kripke_census_result* graph_out = nullptr;
   int ls = -1;   // frame sets per lane (log2) of the fused launch, -1 = none
   int ipw = 16;  // work items per wave
+  Tiering tiers;
   bool plain = false;  // one launch per formula, no graph
 };
 
@@ -602,12 +679,13 @@ static void tune_store(const char* path, const std::string& key, int ls, int ipw
 static int tune_plan(KripkePlan* p, const char* path) {
   const std::string key = tune_key(p);
   int ls = p->ls, ipw = p->ipw;
-  if (tune_lookup(path, key, &ls, &ipw) && ls >= 0 && ls <= 2 &&
-      fast_available(p->n, p->nvars, ls, 0, true) && p->mb.max_slots <= fast_slots(ls) &&
-      ipw > 0) {
+  Tiering t;
+  if (tune_lookup(path, key, &ls, &ipw) && ipw > 0 &&
+      make_tiers(p->mb, p->n, p->nvars, 0, true, ls, &t)) {
     p->ls = ls;
     p->ipw = ipw;
-    return KRIPKE_OK;
+    p->tiers = t;
+    return upload_order(t, p->db.order, p->cap);
   }
   kripke_census_result* scratch = nullptr;
   KR_HIP(hipMalloc(&scratch, sizeof(kripke_census_result) * 4 * p->nformulas));
@@ -617,8 +695,11 @@ static int tune_plan(KripkePlan* p, const char* path) {
   const uint64_t slice = std::min<uint64_t>(1ull << (p->n * p->n), 1ull << 20);
   double best = 1e300;
   int best_ls = p->ls, best_ipw = p->ipw;
-  for (int l = 0; l <= 2; ++l) {
-    if (!fast_available(p->n, p->nvars, l, 0, true) || p->mb.max_slots > fast_slots(l)) continue;
+  for (int l = 0; l <= 3; ++l) {
+    if (!make_tiers(p->mb, p->n, p->nvars, 0, true, l, &t)) continue;
+    p->tiers = t;
+    int rc0 = upload_order(t, p->db.order, p->cap);
+    if (rc0) return rc0;
     for (int w : {4, 16, 64}) {
       p->ls = l;
       p->ipw = w;
@@ -639,6 +720,8 @@ static int tune_plan(KripkePlan* p, const char* path) {
   }
   p->ls = best_ls;
   p->ipw = best_ipw;
+  make_tiers(p->mb, p->n, p->nvars, 0, true, best_ls, &p->tiers);
+  if (int rc1 = upload_order(p->tiers, p->db.order, p->cap)) return rc1;
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   KR_HIP(hipFree(scratch));
@@ -707,8 +790,9 @@ int kripke_plan_create(const uint8_t* code, const uint32_t* offsets, uint32_t nf
         return rc;
       }
   // tables used inside the captured graph must exist before capture
-  if (class_mask == 0xF && n <= 5 && !plain)
-    p->ls = pick_sets((int)n, (int)nvars, 0, true, p->mb.max_slots);
+  if (class_mask == 0xF && n <= 5 && !plain && pick_tiers(p->mb, (int)n, (int)nvars, 0, true,
+                                                            &p->tiers))
+    p->ls = p->tiers.ls_a;
   if (p->ls >= 0) {
     const uint32_t* lv = nullptr;
     if ((rc = level_table(p->ds, (int)n, &lv))) {
@@ -721,7 +805,8 @@ int kripke_plan_create(const uint8_t* code, const uint32_t* offsets, uint32_t nf
     delete p;
     return fail(KRIPKE_EHIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
   }
-  if ((rc = upload(p->mb, &p->db, 4, p->cap))) {
+  if ((rc = upload(p->mb, &p->db, 4, p->cap)) ||
+      (p->ls >= 0 && (rc = upload_order(p->tiers, p->db.order, p->cap)))) {
     hipStreamDestroy(p->cap);
     delete p;
     return rc;
@@ -738,11 +823,11 @@ int kripke_plan_create(const uint8_t* code, const uint32_t* offsets, uint32_t nf
 static int plan_enqueue(KripkePlan* p, kripke_census_result* d_out, hipStream_t s,
                         uint64_t frames) {
   const uint64_t nf = frames ? frames : 1ull << (p->n * p->n);
-  if (p->ls >= 0)  // one launch: every K frame reduces into each class containing it
-    return enqueue_fast(p->ds, p->db, p->n, p->nvars, p->ls, 0, true, p->nformulas, 0, nf,
-                        reinterpret_cast<unsigned long long*>(&d_out[0].first_key),
-                        reinterpret_cast<unsigned long long*>(&d_out[0].fail_count), false,
-                        p->db.queue, s, p->ipw);
+  if (p->ls >= 0)  // one pass: every K frame reduces into each class containing it
+    return enqueue_tiered(p->ds, p->db, p->tiers, p->n, p->nvars, 0, true, p->nformulas, 0, nf,
+                          reinterpret_cast<unsigned long long*>(&d_out[0].first_key),
+                          reinterpret_cast<unsigned long long*>(&d_out[0].fail_count), false,
+                          p->db.queue, s, p->ipw);
   for (int c = 0; c < 4; ++c) {
     if (!((p->class_mask >> c) & 1u)) continue;
     kripke_census_result* row = d_out + (size_t)c * p->nformulas;

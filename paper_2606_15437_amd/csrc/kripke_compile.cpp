@@ -11,6 +11,7 @@
 //     Sethi-Ullman rule so the stack of saved truth sets stays shallow, and a
 //     literal operand is consumed directly instead of being loaded.
 #include <algorithm>
+#include <vector>
 #include <cstdio>
 
 #include "kripke_internal.h"
@@ -178,11 +179,30 @@ struct Emitter {
         out->loads++;
         return;
       case K_BOX:
-      case K_DIA:
-        emit(n.a, depth);
-        m.push_back(n.kind == K_BOX ? U_BOX : U_DIA);
-        out->modal++;
+      case K_DIA: {
+        // a chain of modal operators over its innermost operand: a literal
+        // operand is consumed by the first modal op, the rest go in pairs
+        std::vector<int> chain;  // outermost first
+        int x = i;
+        while (B.nodes[x].kind == K_BOX || B.nodes[x].kind == K_DIA) {
+          chain.push_back(B.nodes[x].kind == K_DIA ? 1 : 0);
+          x = B.nodes[x].a;
+        }
+        out->modal += (int)chain.size();
+        size_t k = chain.size();  // next modal op to apply is chain[k-1]
+        if (leaf(x) && B.nodes[x].leaf < L_SUCC) {
+          m.push_back((uint8_t)((chain[k - 1] ? U_DIA_L : U_BOX_L) + B.nodes[x].leaf));
+          --k;
+        } else {
+          emit(x, depth);
+        }
+        while (k >= 2) {
+          m.push_back((uint8_t)(U_MM + 2 * chain[k - 1] + chain[k - 2]));
+          k -= 2;
+        }
+        if (k == 1) m.push_back(chain[0] ? U_DIA : U_BOX);
         return;
+      }
       default: break;
     }
     uint8_t base_l = n.kind == K_AND ? U_AND_L : n.kind == K_OR ? U_OR_L : U_IFF_L;

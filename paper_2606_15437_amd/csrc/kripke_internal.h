@@ -41,7 +41,11 @@ enum : uint8_t {
   U_AND_S = 53,   // + d: ACC = slot[d] & ACC
   U_OR_S = 61,    // + d
   U_IFF_S = 69,   // + d
-  U_NCODES = 77
+  // superinstructions (one dispatch for a common pair)
+  U_DIA_L = 77,   // + leaf (0..9): ACC = DIA leaf
+  U_BOX_L = 87,   // + leaf (0..9): ACC = BOX leaf
+  U_MM = 97,      // + 2*first + second (modal 0 BOX, 1 DIA): ACC = second(first(ACC))
+  U_NCODES = 101
 };
 
 constexpr int kMaxSlots = 8;

@@ -270,6 +270,48 @@ def test_fused_plan_small_classes_vs_oracle(kr, orc):
         assert (r[c, :, 0] == ek).all() and (r[c, :, 1] == ec).all(), c
 
 
+def _deep_formulas():
+    """Programs whose compiled form needs 3 stack slots (balanced trees of modal literals),
+    so a batch holding them runs as two tiers of kernel variants."""
+    u = ["<>p", "[]q", "<>~q", "[]~p", "<>(p & q)", "[](p | ~q)", "<>[]p", "[]<>q"]
+    pairs = [f"({u[i]} & {u[i + 1]})" for i in range(0, 8, 2)]
+    quads = [f"({pairs[0]} | {pairs[1]})", f"({pairs[2]} | {pairs[3]})"]
+    return [I.parse(f"{quads[0]} <-> {quads[1]}"), I.parse(f"{quads[0]} & {quads[1]}"),
+            I.parse(f"~({quads[1]} -> {quads[0]})")]
+
+
+def test_tiered_batch_against_oracle(kr, orc):
+    from paper_2606_15437_amd.inputs import pack
+    fs = I.config3_formulas()[:40] + _deep_formulas()
+    st = kr.kripke_program_stats(*pack(fs), 2)
+    assert st[:, 4].max() >= 3  # the batch really needs a second tier
+    f0 = (1 << 22) + 12345
+    keys, cnts = kr.census(fs, 5, 0, 2, frame_begin=f0, frame_end=f0 + 200)
+    ek, ec = _oracle_all(orc, fs, 5, 0, 2, f0, f0 + 200)
+    assert (keys == ek).all() and (cnts == ec).all()
+    f0 = (1 << 24) | (1 << 18) | (1 << 12) | 64
+    keys, cnts = kr.census(fs, 5, 1, 2, frame_begin=f0, frame_end=f0 + 300)
+    ek, ec = _oracle_all(orc, fs, 5, 1, 2, f0, f0 + 300)
+    assert (keys == ek).all() and (cnts == ec).all()
+
+
+def test_tiered_fused_plan(kr):
+    import torch
+    fs = I.config3_formulas()[200:260] + _deep_formulas()
+    code, offs = I.pack(fs)
+    out = torch.zeros((4, len(fs), 2), dtype=torch.int64, device="cuda")
+    plan = kr.kripke_plan_create(code, offs, 5, 0xF, 2)
+    try:
+        kr.kripke_plan_launch(plan, out)
+        torch.cuda.synchronize()
+        r = kr.as_u64(out)
+    finally:
+        kr.kripke_plan_destroy(plan)
+    for c in CLASSES:
+        k, n = kr.census(fs, 5, c, 2)
+        assert (r[c, :, 0] == k).all() and (r[c, :, 1] == n).all(), c
+
+
 # ------------------------------------------------------------- split
 @pytest.mark.parametrize("n", [6, 7, 8])
 def test_split_parity_families(kr, orc, n):
