@@ -62,6 +62,9 @@ def main():
                                                          "tune_cache.json"))
     ap.add_argument("--cpu-frames-log2", type=int, default=14)
     ap.add_argument("--cpu-formulas", type=int, default=64)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (reference for "
+                         "HBM byte counters)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -86,6 +89,13 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     calib = K.kripke_calibrate_int32(stream)
     log(f"INT32 VALU calibration: {calib / 1e12:.2f} T lane-ops/s "

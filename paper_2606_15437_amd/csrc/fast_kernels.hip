@@ -79,8 +79,21 @@ struct Geo {
   static constexpr int S = 1 << LS;                              // frame sets per lane
   static constexpr int B = LF + LS;                              // log2 frames per block
   static constexpr int CHB = V > 11 ? V - 11 : 0;                // valuation chunk bits
-  static constexpr int DS = LS == 0 ? 4 : LS <= 2 ? 2 : 1;       // stack slots
+  static constexpr int DS = LS == 0 ? 4 : LS <= 2 ? 2 : 1;       // stack slots in registers
+  static constexpr int LDS_SLOTS = 1;                            // + slots spilled to LDS
 };
+
+// Diagonal positions whose relation bit is shared by the whole block (mode K):
+// a block can hold a reflexive frame only if all of them are set.
+template <int N, int NV, int LS, int MODE>
+__host__ __device__ constexpr uint64_t diag_uniform_mask() {
+  uint64_t m = 0;
+  for (int w = 0; w < N; ++w) {
+    const int p = w * N + w;
+    if (MODE == 0 && p >= Geo<N, NV, LS, MODE>::B) m |= 1ull << p;
+  }
+  return m;
+}
 
 template <int N, int NV, int LS, int MODE>
 struct Ctx {
@@ -92,6 +105,8 @@ struct Ctx {
   uint32_t ch[G::CHB > 0 ? G::CHB : 1]; // uniform valuation-chunk words
   uint32_t acc[G::S][N];
   uint32_t stk[G::DS][G::S][N];
+  uint32_t* spill;  // this wave's LDS overflow slots: [LDS_SLOTS][S][N][64 lanes]
+  int lane;
 };
 
 template <int N, int NV, int LS, int MODE>
@@ -121,7 +136,10 @@ __device__ __forceinline__ uint32_t leaf(const Ctx<N, NV, LS, MODE>& c, int s, i
   } else if constexpr (L < 8) {
     return ~var_word(c, L - 4, w);
   } else if constexpr (L == L_SUCC || L == L_DEAD) {
-    uint32_t r = 0;
+    // "has a successor": an OR over the row, seeded opaquely so it is
+    // computed where used instead of being hoisted for every block
+    uint32_t r;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(r));
 #pragma unroll
     for (int v = 0; v < N; ++v) r |= rel(c, s, w, v);
     return L == L_SUCC ? r : ~r;
@@ -190,19 +208,27 @@ template <int N, int NV, int LS, int MODE, int L>
 __device__ __forceinline__ void f_or(Ctx<N, NV, LS, MODE>& c) { f_bin_leaf<1, N, NV, LS, MODE, L>(c); }
 template <int N, int NV, int LS, int MODE, int L>
 __device__ __forceinline__ void f_iff(Ctx<N, NV, LS, MODE>& c) { f_bin_leaf<2, N, NV, LS, MODE, L>(c); }
+// Stack slots below DS live in registers; the next LDS_SLOTS spill to the
+// wave's LDS area (rare: only programs needing the extra slot touch it).
 template <int N, int NV, int LS, int MODE, int D>
 __device__ __forceinline__ void f_save(Ctx<N, NV, LS, MODE>& c) {
-  if constexpr (D < Geo<N, NV, LS, MODE>::DS) {
+  using G = Geo<N, NV, LS, MODE>;
+  if constexpr (D < G::DS) {
     KR_FOR_SW c.stk[D][s][w] = c.acc[s][w];
+  } else if constexpr (D < G::DS + G::LDS_SLOTS) {
+    KR_FOR_SW c.spill[(((D - G::DS) * G::S + s) * N + w) * 64 + c.lane] = c.acc[s][w];
   }
 }
 template <int N, int NV, int LS, int MODE, int D, int OP>
 __device__ __forceinline__ void f_comb(Ctx<N, NV, LS, MODE>& c) {
-  if constexpr (D < Geo<N, NV, LS, MODE>::DS) {
+  using G = Geo<N, NV, LS, MODE>;
+  if constexpr (D < G::DS + G::LDS_SLOTS) {
     KR_FOR_SW {
-      if constexpr (OP == 0) c.acc[s][w] &= c.stk[D][s][w];
-      else if constexpr (OP == 1) c.acc[s][w] |= c.stk[D][s][w];
-      else c.acc[s][w] = ~(c.acc[s][w] ^ c.stk[D][s][w]);
+      const uint32_t y = D < G::DS ? c.stk[D < G::DS ? D : 0][s][w]
+                                   : c.spill[(((D - G::DS) * G::S + s) * N + w) * 64 + c.lane];
+      if constexpr (OP == 0) c.acc[s][w] &= y;
+      else if constexpr (OP == 1) c.acc[s][w] |= y;
+      else c.acc[s][w] = ~(c.acc[s][w] ^ y);
     }
   }
 }
@@ -282,9 +308,10 @@ __device__ __forceinline__ void f_modal_leaf(Ctx<N, NV, LS, MODE>& c) {
   case BASE + 0: FN(0); break; case BASE + 1: FN(1); break; case BASE + 2: FN(2); break; \
   case BASE + 3: FN(3); break; case BASE + 4: FN(4); break; case BASE + 5: FN(5); break; \
   case BASE + 6: FN(6); break; case BASE + 7: FN(7); break;
-#define KR_D4(BASE, FN) \
+#define KR_D8(BASE, FN) \
   case BASE + 0: FN(0); break; case BASE + 1: FN(1); break; case BASE + 2: FN(2); break; \
-  case BASE + 3: FN(3); break;
+  case BASE + 3: FN(3); break; case BASE + 4: FN(4); break; case BASE + 5: FN(5); break; \
+  case BASE + 6: FN(6); break; case BASE + 7: FN(7); break;
 
 // Interpret the wave's program (staged in LDS, 8-byte padded) on the current
 // block.  Ops are consumed from a 64-bit shift register holding the next
@@ -324,10 +351,10 @@ __device__ __forceinline__ void run(Ctx<N, NV, LS, MODE>& c, const uint32_t* pro
       KR_L10(U_IFF_L, G_IFF)
       case U_BOX: f_modal<false, N, NV, LS, MODE>(c); break;
       case U_DIA: f_modal<true, N, NV, LS, MODE>(c); break;
-      KR_D4(U_SAVE, G_SAVE)
-      KR_D4(U_AND_S, G_ANDS)
-      KR_D4(U_OR_S, G_ORS)
-      KR_D4(U_IFF_S, G_IFFS)
+      KR_D8(U_SAVE, G_SAVE)
+      KR_D8(U_AND_S, G_ANDS)
+      KR_D8(U_OR_S, G_ORS)
+      KR_D8(U_IFF_S, G_IFFS)
       KR_L8(U_DIA_L, G_DIAL)
       KR_L8(U_BOX_L, G_BOXL)
       case U_MM + 0: f_modal<false, N, NV, LS, MODE>(c); f_modal<false, N, NV, LS, MODE>(c); break;
@@ -376,12 +403,15 @@ __global__ __launch_bounds__(256) void census_fast(FastArgs a) {
   using G = Geo<N, NV, LS, MODE>;
   static_assert(G::V >= 5, "fast kernel needs n * nvars >= 5");
   __shared__ uint32_t sprog[4][kMaxMicro / 4 + 4];
+  __shared__ uint32_t sspill[4][G::LDS_SLOTS * G::S * N * 64];
   const int lane = threadIdx.x & 63;
   uint32_t* prog = sprog[threadIdx.x >> 6];
   constexpr int NC = FUSED ? 4 : 1;
   const uint64_t blk_end = a.blk_begin + a.nblk;
 
   Ctx<N, NV, LS, MODE> c;
+  c.spill = sspill[threadIdx.x >> 6];
+  c.lane = lane;
   // Patterns live in vector registers on purpose: a modal term combines a
   // scalar relation word with a pattern, and an instruction takes at most one
   // scalar operand.
@@ -455,7 +485,9 @@ __global__ __launch_bounds__(256) void census_fast(FastArgs a) {
       // class levels of the block's frames; consumed only after evaluation,
       // so the scalar load overlaps the interpreter
       uint32_t lvl_raw = 0;
-      if (FUSED) lvl_raw = a.levels[pbase >> 4];
+      constexpr uint64_t kDiag = diag_uniform_mask<N, NV, LS, MODE>();
+      if (FUSED && (base & kDiag) == kDiag)
+        lvl_raw = a.levels[pbase >> 4];
       uint64_t best[NC];
 #pragma unroll
       for (int k = 0; k < NC; ++k) best[k] = ~0ull;

@@ -306,8 +306,9 @@ int enqueue_scan(DeviceState* ds, const DeviceBatch& db, const Scan& sc, int n, 
   return KRIPKE_OK;
 }
 
-// Stack slots of the fast kernel variant with 2^ls frame sets per lane.
-int fast_slots(int ls) { return ls == 0 ? 4 : ls <= 2 ? 2 : 1; }
+// Stack slots of the fast kernel variant with 2^ls frame sets per lane:
+// register slots plus one LDS overflow slot.
+int fast_slots(int ls) { return (ls == 0 ? 4 : ls <= 2 ? 2 : 1) + 1; }
 
 // Preferred number of frame sets per lane (log2) for the fast kernel, or -1
 // if no variant fits; KRIPKE_SETS_LOG2 overrides the default for tuning.
