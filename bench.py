@@ -36,6 +36,20 @@ PEAK_INT32 = 256 * 128 * 2.4e9
 CLASS_FRAMES_N5 = (33554432, 1048576, 6942, 52)
 
 
+def recorded_traffic():
+    """HBM bytes per launch of the census kernel from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE record, or None if the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "census_fast_n5_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -191,7 +205,8 @@ def main():
                    "formulas": B, "n": n, "nvars": nvars, "evals_per_step": evals_step,
                    "no_countermodel_per_class": valid},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32 / 1e12,
-                     "unit": "T INT32 ops/s", "frac": achieved / PEAK_INT32, "traffic": None,
+                     "unit": "T INT32 ops/s", "frac": achieved / PEAK_INT32,
+                     "traffic": recorded_traffic(),
                      "kernel": "census_fast<5,2,*,K,fused>",
                      "measured_int32_ceiling": calib / 1e12,
                      "frac_of_measured_ceiling": achieved / calib,
