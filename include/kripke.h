@@ -173,6 +173,79 @@ int kripke_program_stats(const uint8_t *code, const uint32_t *offsets, uint32_t 
  */
 int kripke_calibrate_int32(double *lane_ops_per_s, void *stream);
 
+/* ------------------------------------------------------------------
+ * Learned pair proposal (candidate generation and ranking before exact
+ * verification; the paper's analogue is representation-guided retrieval in
+ * Section 9 followed by exhaustive rescans).
+ * ------------------------------------------------------------------ */
+
+/*
+ * kripke_signatures -- truth bits of each formula at a list of pointed
+ * models (Section 2 satisfaction), used as a semantic signature.
+ * samples: HOST array of nsamples packed models
+ *   n << 60 | frame << 24 | valuation << 4 | world   (1 <= n <= 3),
+ * nsamples a multiple of 64, each aligned run of 64 samples with one n.
+ * d_sig: DEVICE uint64[nformulas][nsamples / 64]; bit s%64 of word s/64 of
+ * row i is 1 iff formula i holds at sample s.
+ */
+int kripke_signatures(const uint8_t *code, const uint32_t *offsets, uint32_t nformulas,
+                      uint32_t nvars, const uint64_t *samples, uint32_t nsamples,
+                      uint64_t *d_sig, void *stream);
+
+/*
+ * kripke_knn_pairs -- candidate pairs: for every formula its k nearest
+ * formulas by signature Hamming distance (ties to the smaller index), as
+ * unordered pairs (i < j) packed i << 32 | j, deduplicated and in canonical
+ * (i, j) order.  d_sig: DEVICE [nformulas][words] (words*64 <= 8192,
+ * nformulas <= 16384, 0 < k < nformulas).  d_pairs: DEVICE uint64 capacity
+ * nformulas*k; d_npairs: DEVICE uint64 (count written).
+ */
+int kripke_knn_pairs(const uint64_t *d_sig, uint32_t nformulas, uint32_t words, uint32_t k,
+                     uint64_t *d_pairs, uint64_t *d_npairs, void *stream);
+
+/* Signature Hamming distance of each pair (d_pairs packed as above). */
+int kripke_pair_hamming(const uint64_t *d_sig, uint32_t words, const uint64_t *d_pairs,
+                        uint64_t npairs, uint32_t *d_dist, void *stream);
+
+/*
+ * kripke_select_top -- indices of the `budget` largest of n float scores,
+ * largest first, equal scores in increasing index order.  All DEVICE
+ * pointers; d_idx holds min(budget, n) uint64.
+ */
+int kripke_select_top(const float *d_scores, uint64_t n, uint64_t budget, uint64_t *d_idx,
+                      void *stream);
+
+/*
+ * Pair-scoring MLP (spec learned proposal): input
+ * [sig_a XOR sig_b, sig_a AND sig_b] of two 4,096-bit signatures (8,192
+ * values in {0,1}) -> 512 -> 256 -> 1, ReLU; BF16 weights and activations as
+ * matrix-core operands, FP32 accumulation, FP32 master weights, Adam.
+ * Parameters (FP32, 4,326,401 values, in this order): W1 [512][8192],
+ * b1 [512], W2 [256][512], b2 [256], w3 [256], b3 [1]; W is (out x in).
+ * Pairs are DEVICE uint64 packed a << 32 | b (row indices of d_sig); d_sig
+ * is DEVICE uint64 [rows][words] with words = 64.
+ */
+int kripke_mlp_create(uint64_t seed, uint32_t max_batch, void **mlp);
+int kripke_mlp_destroy(void *mlp);
+/* Host copies of the FP32 parameters / gradients (4,326,401 floats). */
+int kripke_mlp_get_params(void *mlp, float *params);
+/* Replace the parameters (and reset the Adam moments and step count). */
+int kripke_mlp_set_params(void *mlp, const float *params);
+int kripke_mlp_get_grads(void *mlp, float *grads);
+/* Logits of npairs pairs (any count; processed in chunks of max_batch). */
+int kripke_mlp_forward(void *mlp, const uint64_t *d_sig, uint32_t words, const uint64_t *d_pairs,
+                       uint64_t npairs, float *d_logits, void *stream);
+/* Mean BCE-with-logits loss (positive weight pos_weight) of one batch of m
+ * labelled pairs (m a multiple of 64, m <= max_batch) and all parameter
+ * gradients, kept inside the handle.  d_labels: DEVICE float[m] in {0,1};
+ * d_loss: DEVICE float[1]. */
+int kripke_mlp_gradients(void *mlp, const uint64_t *d_sig, uint32_t words,
+                         const uint64_t *d_pairs, const float *d_labels, uint32_t m,
+                         float pos_weight, float *d_loss, void *stream);
+/* One Adam step (bias-corrected) from the gradients of the last
+ * kripke_mlp_gradients call; refreshes the BF16 working copies. */
+int kripke_mlp_adam_step(void *mlp, float lr, float beta1, float beta2, float eps, void *stream);
+
 /* Message for the last failure on this thread ("" if none). */
 const char *kripke_last_error(void);
 

@@ -63,6 +63,29 @@ hipError_t launch_levels(int n, uint32_t* levels, hipStream_t s);
 uint64_t refl_frame_host(uint64_t j, int n);
 hipError_t run_calibration(int cus, uint32_t iters, double* lane_ops_per_s, hipStream_t s);
 
+// Signature bits: formulas x groups of 64 pointed-model samples of one n.
+struct SigArgs {
+  const uint8_t* ucode;
+  const uint32_t* uoff;
+  uint32_t nformulas;
+  const uint64_t* samples;  // n << 60 | frame << 24 | val << 4 | world
+  const uint32_t* groups;   // indices of the 64-sample groups with this n
+  uint32_t ngroups;
+  uint32_t words;           // signature words per formula (all groups)
+  unsigned long long* sig;  // [nformulas][words]
+};
+hipError_t launch_signatures(const SigArgs& a, int n, int nvars, hipStream_t s);
+
+// Candidate pairs: the k nearest formulas of each formula by signature
+// Hamming distance, then the unordered pairs in canonical order.
+hipError_t launch_knn(const uint64_t* sig, uint32_t nformulas, uint32_t words, uint32_t k,
+                      uint32_t* nbr, hipStream_t s);
+int knn_pairs_canonical(const uint32_t* nbr, uint32_t nformulas, uint32_t k, uint64_t* pairs,
+                        uint64_t* npairs, hipStream_t s);
+hipError_t launch_pair_hamming(const uint64_t* sig, uint32_t words, const uint64_t* pairs,
+                               uint64_t npairs, uint32_t* dist, hipStream_t s);
+int select_top(const float* scores, uint64_t n, uint64_t budget, uint64_t* idx, hipStream_t s);
+
 hipError_t launch_census(const CensusArgs& a, int n, int nvars, int grid, hipStream_t s);
 int census_blocks_per_cu(int n, int nvars);
 hipError_t launch_init(unsigned long long* key, unsigned long long* cnt, uint32_t stride,

@@ -18,6 +18,7 @@
 // the 64 lanes evaluate 64 (frame, valuation-word) units in lock step.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kripke_internal.h"
@@ -340,6 +341,56 @@ __global__ __launch_bounds__(256) void census_generic(CensusArgs a) {
   }
 }
 
+// ----------------------------------------------------------- signatures
+// Truth bits of formulas at sampled pointed models (n, frame, valuation,
+// world), 64 samples per wavefront: each lane evaluates its sample's frame
+// on the 32-valuation word holding the sample's valuation and keeps one bit;
+// a ballot packs the 64 bits into one word of the signature.
+template <int N, int NV>
+__global__ __launch_bounds__(256) void signature_kernel(SigArgs a) {
+  constexpr int V = N * NV;
+  __shared__ uint32_t sprog[4][kMaxMicro / 4 + 4];
+  const int lane = threadIdx.x & 63;
+  uint32_t* prog = sprog[threadIdx.x >> 6];
+  const uint64_t total = (uint64_t)a.nformulas * a.ngroups;
+  const uint64_t wave = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint64_t stride = (uint64_t)gridDim.x * 4;
+  uint32_t staged = ~0u;
+  Regs<N, NV> r;
+  for (uint64_t item = wave; item < total; item += stride) {
+    const uint32_t f = (uint32_t)(item / a.ngroups);
+    const uint32_t g = a.groups[item % a.ngroups];
+    if (f != staged) {
+      const uint32_t p0 = a.uoff[f] >> 2, pw = (a.uoff[f + 1] >> 2) - p0;
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(a.ucode) + p0;
+      __builtin_amdgcn_wave_barrier();
+      for (uint32_t i = lane; i < pw; i += 64) prog[i] = src[i];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      staged = f;
+    }
+    const uint64_t smp = a.samples[(uint64_t)g * 64 + lane];
+    const uint64_t frame = (smp >> 24) & 0xFFFFFFFFFull;
+    const uint32_t val = (uint32_t)(smp >> 4) & 0xFFFFFu;
+    const uint32_t world = (uint32_t)(smp & 15u);
+#pragma unroll
+    for (int w = 0; w < N; ++w)
+#pragma unroll
+      for (int v = 0; v < N; ++v) r.R[w][v] = 0u - (uint32_t)((frame >> (w * N + v)) & 1u);
+    const uint32_t word = V > 5 ? (val >> 5) : 0u;
+#pragma unroll
+    for (int i = 0; i < Regs<N, NV>::kVat; ++i) r.vat[i] = 0u - ((word >> i) & 1u);
+    interpret<N, NV>(r, prog);
+    uint32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < N; ++w)
+      if ((uint32_t)w == world) t = r.acc[w];
+    const uint64_t bits = __ballot(((t >> (val & 31u)) & 1u) != 0);
+    if (lane == 0) a.sig[(uint64_t)f * a.words + g] = bits;
+  }
+}
+
 // ------------------------------------------------------- helper kernels
 __global__ void init_results(unsigned long long* key, unsigned long long* cnt, uint32_t stride,
                              uint32_t count, unsigned long long* queue) {
@@ -424,6 +475,22 @@ __global__ void class_scatter(int n, int level, uint64_t nframes, const uint32_t
 }
 
 // ------------------------------------------------------------ dispatch
+hipError_t launch_signatures(const SigArgs& a, int n, int nvars, hipStream_t s) {
+  const uint64_t total = (uint64_t)a.nformulas * a.ngroups;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((total + 3) / 4, 256u * 64u);
+  if (total == 0) return hipSuccess;
+#define KR_SIG(N, NV)                                                                     \
+  if (n == N && nvars == NV) {                                                           \
+    hipLaunchKernelGGL((signature_kernel<N, NV>), dim3(grid), dim3(256), 0, s, a);        \
+    return hipGetLastError();                                                             \
+  }
+  KR_SIG(1, 0) KR_SIG(1, 1) KR_SIG(1, 2) KR_SIG(1, 3) KR_SIG(1, 4)
+  KR_SIG(2, 0) KR_SIG(2, 1) KR_SIG(2, 2) KR_SIG(2, 3) KR_SIG(2, 4)
+  KR_SIG(3, 0) KR_SIG(3, 1) KR_SIG(3, 2) KR_SIG(3, 3) KR_SIG(3, 4)
+#undef KR_SIG
+  return hipErrorInvalidValue;
+}
+
 template <int N, int NV>
 static hipError_t launch_one(const CensusArgs& a, int grid, hipStream_t s) {
   hipLaunchKernelGGL((census_generic<N, NV>), dim3(grid), dim3(256), 0, s, a);

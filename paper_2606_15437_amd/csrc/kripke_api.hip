@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -14,6 +15,7 @@
 
 #include "../../include/kripke.h"
 #include "census_kernels.h"
+#include "mlp_kernels.h"
 #include "kripke_internal.h"
 
 using namespace kripke;
@@ -749,6 +751,223 @@ int kripke_program_stats(const uint8_t* code, const uint32_t* offsets, uint32_t 
     o[4] = c.slots;
     o[5] = c.is_const;
   }
+  return KRIPKE_OK;
+}
+
+int kripke_signatures(const uint8_t* code, const uint32_t* offsets, uint32_t nformulas,
+                      uint32_t nvars, const uint64_t* samples, uint32_t nsamples, uint64_t* d_sig,
+                      void* stream) {
+  g_err.clear();
+  if (!samples || !d_sig || nformulas == 0) return fail(KRIPKE_EINVAL, "null pointer or empty batch");
+  if (nsamples == 0 || nsamples % 64) return fail(KRIPKE_EINVAL, "nsamples must be a multiple of 64");
+  if (nvars > 4) return fail(KRIPKE_ELIMIT, "nvars must be <= 4");
+  const uint32_t ngroups = nsamples / 64;
+  std::vector<uint32_t> groups[4];
+  for (uint32_t g = 0; g < ngroups; ++g) {
+    const uint32_t n = (uint32_t)(samples[g * 64ull] >> 60);
+    for (uint32_t l = 0; l < 64; ++l) {
+      const uint64_t smp = samples[g * 64ull + l];
+      const uint32_t sn = (uint32_t)(smp >> 60);
+      const uint64_t f = (smp >> 24) & 0xFFFFFFFFFull;
+      const uint64_t val = (smp >> 4) & 0xFFFFFu;
+      if (sn != n || n < 1 || n > 3 || f >= (1ull << (n * n)) || val >= (1ull << (nvars * n)) ||
+          (smp & 15u) >= n)
+        return fail(KRIPKE_EINVAL, "sample " + std::to_string(g * 64 + l) + " is invalid or "
+                                   "its group of 64 mixes world counts");
+    }
+    groups[n].push_back(g);
+  }
+  MicroBatch mb;
+  int rc;
+  if ((rc = compile_batch(code, offsets, nformulas, nvars, 3, false, &mb))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  DeviceBatch db;
+  if ((rc = upload(mb, &db, 1, s))) return rc;
+  uint64_t* d_samples = nullptr;
+  uint32_t* d_groups = nullptr;
+  KR_HIP(hipMallocAsync((void**)&d_samples, nsamples * 8ull, s));
+  KR_HIP(hipMallocAsync((void**)&d_groups, ngroups * 4ull, s));
+  KR_HIP(hipMemcpyAsync(d_samples, samples, nsamples * 8ull, hipMemcpyHostToDevice, s));
+  std::vector<uint32_t> all;
+  for (int n = 1; n <= 3; ++n) all.insert(all.end(), groups[n].begin(), groups[n].end());
+  KR_HIP(hipMemcpyAsync(d_groups, all.data(), all.size() * 4, hipMemcpyHostToDevice, s));
+  KR_HIP(hipStreamSynchronize(s));
+  uint32_t at = 0;
+  for (int n = 1; n <= 3; ++n) {
+    if (groups[n].empty()) continue;
+    SigArgs a{};
+    a.ucode = db.ucode;
+    a.uoff = db.uoff;
+    a.nformulas = nformulas;
+    a.samples = d_samples;
+    a.groups = d_groups + at;
+    a.ngroups = (uint32_t)groups[n].size();
+    a.words = ngroups;
+    a.sig = reinterpret_cast<unsigned long long*>(d_sig);
+    KR_HIP(launch_signatures(a, n, (int)nvars, s));
+    at += a.ngroups;
+  }
+  KR_HIP(hipFreeAsync(d_samples, s));
+  KR_HIP(hipFreeAsync(d_groups, s));
+  return release(&db, s);
+}
+
+int kripke_knn_pairs(const uint64_t* d_sig, uint32_t nformulas, uint32_t words, uint32_t k,
+                     uint64_t* d_pairs, uint64_t* d_npairs, void* stream) {
+  g_err.clear();
+  if (!d_sig || !d_pairs || !d_npairs) return fail(KRIPKE_EINVAL, "null pointer");
+  if (nformulas > 16384 || words == 0 || words * 64 > 8192 || k == 0 || k >= nformulas)
+    return fail(KRIPKE_ELIMIT, "need nformulas <= 16384, 0 < words*64 <= 8192, 0 < k < nformulas");
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t* nbr = nullptr;
+  KR_HIP(hipMallocAsync((void**)&nbr, (uint64_t)nformulas * k * 4, s));
+  KR_HIP(launch_knn(d_sig, nformulas, words, k, nbr, s));
+  int rc = knn_pairs_canonical(nbr, nformulas, k, d_pairs, d_npairs, s);
+  if (rc) return fail(rc, "pair sort failed");
+  KR_HIP(hipFreeAsync(nbr, s));
+  return KRIPKE_OK;
+}
+
+int kripke_pair_hamming(const uint64_t* d_sig, uint32_t words, const uint64_t* d_pairs,
+                        uint64_t npairs, uint32_t* d_dist, void* stream) {
+  g_err.clear();
+  if (!d_sig || (!d_pairs && npairs) || (!d_dist && npairs)) return fail(KRIPKE_EINVAL, "null pointer");
+  KR_HIP(launch_pair_hamming(d_sig, words, d_pairs, npairs, d_dist, (hipStream_t)stream));
+  return KRIPKE_OK;
+}
+
+int kripke_select_top(const float* d_scores, uint64_t n, uint64_t budget, uint64_t* d_idx,
+                      void* stream) {
+  g_err.clear();
+  if (!d_scores || !d_idx || n == 0) return fail(KRIPKE_EINVAL, "null pointer or empty input");
+  if (n > 0x7FFFFFFFull) return fail(KRIPKE_ELIMIT, "at most 2^31 - 1 scores");
+  int rc = select_top(d_scores, n, budget, d_idx, (hipStream_t)stream);
+  if (rc) return fail(rc, "score sort failed");
+  return KRIPKE_OK;
+}
+
+// ---------------------------------------------------------------- MLP
+int kripke_mlp_create(uint64_t seed, uint32_t max_batch, void** mlp) {
+  g_err.clear();
+  if (!mlp || max_batch == 0 || max_batch % 64 || max_batch > (1u << 20))
+    return fail(KRIPKE_EINVAL, "max_batch must be a positive multiple of 64 (<= 2^20)");
+  auto* S = new MlpState();
+  S->max_batch = max_batch;
+  const uint64_t B = max_batch;
+  struct A { void** p; uint64_t bytes; } allocs[] = {
+      {(void**)&S->params, kParams * 4}, {(void**)&S->grads, kParams * 4},
+      {(void**)&S->m1, kParams * 4},     {(void**)&S->m2, kParams * 4},
+      {(void**)&S->w1b, (uint64_t)kH1 * kIn * 2}, {(void**)&S->w2b, (uint64_t)kH2 * kH1 * 2},
+      {(void**)&S->w2tb, (uint64_t)kH2 * kH1 * 2}, {(void**)&S->a1, B * kH1 * 2},
+      {(void**)&S->a1t, B * kH1 * 2},    {(void**)&S->a2b, B * kH2 * 2},
+      {(void**)&S->a2, B * kH2 * 4},     {(void**)&S->logit, B * 4},
+      {(void**)&S->dz, B * 4},           {(void**)&S->lossv, B * 4},
+      {(void**)&S->dh2f, B * kH2 * 4},   {(void**)&S->dh1f, B * kH1 * 4},
+      {(void**)&S->dh2, B * kH2 * 2},    {(void**)&S->dh2t, B * kH2 * 2},
+      {(void**)&S->dh1t, B * kH1 * 2}};
+  for (auto& a : allocs)
+    if (hipMalloc(a.p, a.bytes) != hipSuccess) {
+      kripke_mlp_destroy(S);
+      return fail(KRIPKE_ENOMEM, "device allocation failed");
+    }
+  // He initialisation, N(0, 2 / fan_in), Box-Muller on SplitMix64 uniforms; biases 0.
+  std::vector<float> p(kParams, 0.f);
+  uint64_t st = seed;
+  auto next = [&]() {
+    st += 0x9E3779B97F4A7C15ull;
+    uint64_t z = st;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  auto gauss = [&]() {
+    const double u1 = ((next() >> 11) + 1.0) / 9007199254740993.0;
+    const double u2 = (next() >> 11) / 9007199254740992.0;
+    return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  };
+  for (uint64_t i = 0; i < (uint64_t)kH1 * kIn; ++i) p[kOffW1 + i] = (float)(gauss() * sqrt(2.0 / kIn));
+  for (uint64_t i = 0; i < (uint64_t)kH2 * kH1; ++i) p[kOffW2 + i] = (float)(gauss() * sqrt(2.0 / kH1));
+  for (uint64_t i = 0; i < kH2; ++i) p[kOffW3 + i] = (float)(gauss() * sqrt(2.0 / kH2));
+  *mlp = S;
+  return kripke_mlp_set_params(S, p.data());
+}
+
+int kripke_mlp_destroy(void* mlp) {
+  auto* S = static_cast<MlpState*>(mlp);
+  if (!S) return KRIPKE_OK;
+  void* ptrs[] = {S->params, S->grads, S->m1, S->m2, S->w1b, S->w2b, S->w2tb, S->a1, S->a1t,
+                  S->a2b, S->a2, S->logit, S->dz, S->lossv, S->dh2f, S->dh1f, S->dh2, S->dh2t,
+                  S->dh1t};
+  for (void* q : ptrs)
+    if (q) hipFree(q);
+  delete S;
+  return KRIPKE_OK;
+}
+
+int kripke_mlp_set_params(void* mlp, const float* params) {
+  g_err.clear();
+  auto* S = static_cast<MlpState*>(mlp);
+  if (!S || !params) return fail(KRIPKE_EINVAL, "null pointer");
+  KR_HIP(hipMemcpy(S->params, params, kParams * 4, hipMemcpyHostToDevice));
+  KR_HIP(hipMemset(S->m1, 0, kParams * 4));
+  KR_HIP(hipMemset(S->m2, 0, kParams * 4));
+  KR_HIP(hipMemset(S->grads, 0, kParams * 4));
+  S->step = 0;
+  KR_HIP(mlp_refresh(*S, nullptr));
+  KR_HIP(hipDeviceSynchronize());
+  return KRIPKE_OK;
+}
+
+int kripke_mlp_get_params(void* mlp, float* params) {
+  g_err.clear();
+  auto* S = static_cast<MlpState*>(mlp);
+  if (!S || !params) return fail(KRIPKE_EINVAL, "null pointer");
+  KR_HIP(hipDeviceSynchronize());
+  KR_HIP(hipMemcpy(params, S->params, kParams * 4, hipMemcpyDeviceToHost));
+  return KRIPKE_OK;
+}
+
+int kripke_mlp_get_grads(void* mlp, float* grads) {
+  g_err.clear();
+  auto* S = static_cast<MlpState*>(mlp);
+  if (!S || !grads) return fail(KRIPKE_EINVAL, "null pointer");
+  KR_HIP(hipDeviceSynchronize());
+  KR_HIP(hipMemcpy(grads, S->grads, kParams * 4, hipMemcpyDeviceToHost));
+  return KRIPKE_OK;
+}
+
+int kripke_mlp_forward(void* mlp, const uint64_t* d_sig, uint32_t words, const uint64_t* d_pairs,
+                       uint64_t npairs, float* d_logits, void* stream) {
+  g_err.clear();
+  auto* S = static_cast<MlpState*>(mlp);
+  if (!S || !d_sig || (npairs && (!d_pairs || !d_logits))) return fail(KRIPKE_EINVAL, "null pointer");
+  if (words != kSigWords) return fail(KRIPKE_ELIMIT, "signatures must have 64 words (4,096 bits)");
+  hipStream_t s = (hipStream_t)stream;
+  for (uint64_t at = 0; at < npairs; at += S->max_batch) {
+    const uint32_t m = (uint32_t)std::min<uint64_t>(S->max_batch, npairs - at);
+    KR_HIP(mlp_forward(*S, d_sig, d_pairs + at, m, d_logits + at, false, s));
+  }
+  return KRIPKE_OK;
+}
+
+int kripke_mlp_gradients(void* mlp, const uint64_t* d_sig, uint32_t words, const uint64_t* d_pairs,
+                         const float* d_labels, uint32_t m, float pos_weight, float* d_loss,
+                         void* stream) {
+  g_err.clear();
+  auto* S = static_cast<MlpState*>(mlp);
+  if (!S || !d_sig || !d_pairs || !d_labels || !d_loss) return fail(KRIPKE_EINVAL, "null pointer");
+  if (words != kSigWords) return fail(KRIPKE_ELIMIT, "signatures must have 64 words (4,096 bits)");
+  if (m == 0 || m % 64 || m > S->max_batch)
+    return fail(KRIPKE_EINVAL, "batch must be a positive multiple of 64, <= max_batch");
+  KR_HIP(mlp_backward(*S, d_sig, d_pairs, d_labels, m, pos_weight, d_loss, (hipStream_t)stream));
+  return KRIPKE_OK;
+}
+
+int kripke_mlp_adam_step(void* mlp, float lr, float beta1, float beta2, float eps, void* stream) {
+  g_err.clear();
+  auto* S = static_cast<MlpState*>(mlp);
+  if (!S) return fail(KRIPKE_EINVAL, "null handle");
+  KR_HIP(mlp_adam(*S, lr, beta1, beta2, eps, (hipStream_t)stream));
   return KRIPKE_OK;
 }
 

@@ -1,0 +1,334 @@
+// Pair-scoring MLP on MFMA: x = [sig_a XOR sig_b, sig_a AND sig_b] (8,192
+// bits) -> 512 -> 256 -> 1, ReLU, BF16 weights and activations as matrix
+// operands, FP32 accumulation, FP32 master weights updated by Adam.
+//
+// Every matrix product is written in "NT" form, C[m][n] = sum_k A(m,k)B(n,k),
+// with both operands contiguous along k, so each lane of a
+// v_mfma_f32_32x32x16_bf16 tile reads its eight k-consecutive values with
+// one 16-byte load (or expands them from eight signature bits).  Layouts:
+//   W1 [512][8192], W2 [256][512] (out x in) for the forward products,
+//   W2T [512][256] for the input gradient of layer 2,
+//   activations stored row-major and, where a weight gradient needs them as
+//   the k-contiguous operand, also transposed.
+// Reductions over the batch (bias and head gradients) run in a fixed order,
+// so training is deterministic.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mlp_kernels.h"
+
+namespace kripke {
+namespace mlp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  // round to nearest even (inputs are finite)
+  const uint32_t u = __float_as_uint(f);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x8 as_bf16x8(u16x8 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// 8 bits -> eight bf16 values 1.0 / 0.0
+__device__ __forceinline__ bf16x8 expand_bits(uint32_t byte) {
+  u16x8 v;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = ((byte >> j) & 1u) ? 0x3F80u : 0u;
+  return as_bf16x8(v);
+}
+
+// ------------------------------------------------------------ loaders
+struct Dense {  // row-major [rows][ld] bf16, k-contiguous
+  const uint16_t* p;
+  uint32_t ld, rows;
+  __device__ __forceinline__ bf16x8 load(uint32_t row, uint32_t k0) const {
+    if (row >= rows) return as_bf16x8(u16x8(0));
+    return as_bf16x8(*reinterpret_cast<const u16x8*>(p + (uint64_t)row * ld + k0));
+  }
+};
+
+// Row m of the pair input: bit k of x_m (k < 4096: XOR, else AND).
+struct PairRows {
+  const uint64_t* sig;
+  const uint64_t* pairs;
+  uint32_t rows;
+  __device__ __forceinline__ bf16x8 load(uint32_t row, uint32_t k0) const {
+    if (row >= rows) return as_bf16x8(u16x8(0));
+    const uint64_t pr = pairs[row];
+    const uint64_t* a = sig + (pr >> 32) * kSigWords;
+    const uint64_t* b = sig + (pr & 0xFFFFFFFFu) * kSigWords;
+    const uint32_t k = k0 & 4095u, w = k >> 6, sh = k & 63u;
+    const uint64_t x = k0 < 4096 ? (a[w] ^ b[w]) : (a[w] & b[w]);
+    return expand_bits((uint32_t)(x >> sh) & 0xFFu);
+  }
+};
+
+// Row f of the transposed pair input: bit f of x_m for m = k0 .. k0+7.
+struct PairCols {
+  const uint64_t* sig;
+  const uint64_t* pairs;
+  uint32_t npairs;
+  __device__ __forceinline__ bf16x8 load(uint32_t f, uint32_t k0) const {
+    const uint32_t k = f & 4095u, w = k >> 6, sh = k & 63u;
+    uint32_t byte = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t m = k0 + j;
+      if (m >= npairs) continue;
+      const uint64_t pr = pairs[m];
+      const uint64_t a = sig[(pr >> 32) * kSigWords + w], b = sig[(pr & 0xFFFFFFFFu) * kSigWords + w];
+      const uint64_t x = f < 4096 ? (a ^ b) : (a & b);
+      byte |= (uint32_t)((x >> sh) & 1u) << j;
+    }
+    return expand_bits(byte);
+  }
+};
+
+// ----------------------------------------------------------- epilogues
+// Layer output: a = relu(acc + bias); bf16 row-major, optional bf16
+// transposed and fp32 row-major copies.
+struct EpiHidden {
+  const float* bias;
+  uint16_t* out;     // [M][N]
+  uint16_t* out_t;   // [N][ldt] or null
+  float* out_f;      // [M][N] or null
+  uint32_t N, ldt;
+  __device__ __forceinline__ void store(uint32_t m, uint32_t n, float acc) const {
+    const float a = fmaxf(acc + bias[n], 0.0f);
+    const uint16_t h = to_bf16(a);
+    out[(uint64_t)m * N + n] = h;
+    if (out_t) out_t[(uint64_t)n * ldt + m] = h;
+    if (out_f) out_f[(uint64_t)m * N + n] = a;
+  }
+};
+
+// Input gradient of a ReLU layer: d = acc where the stored activation is
+// positive, else 0; fp32 row-major (for the bias gradient) and bf16
+// transposed (operand of the weight gradient).
+struct EpiReluGrad {
+  const uint16_t* act;  // [M][N] bf16 activations of that layer
+  float* out_f;         // [M][N]
+  uint16_t* out_t;      // [N][ldt]
+  uint32_t N, ldt;
+  __device__ __forceinline__ void store(uint32_t m, uint32_t n, float acc) const {
+    const float d = from_bf16(act[(uint64_t)m * N + n]) > 0.0f ? acc : 0.0f;
+    out_f[(uint64_t)m * N + n] = d;
+    out_t[(uint64_t)n * ldt + m] = to_bf16(d);
+  }
+};
+
+struct EpiStore {  // plain fp32 row-major
+  float* out;
+  uint32_t N;
+  __device__ __forceinline__ void store(uint32_t m, uint32_t n, float acc) const {
+    out[(uint64_t)m * N + n] = acc;
+  }
+};
+
+// ---------------------------------------------------------------- GEMM
+// Block = 4 waves = a 64x64 tile of C; each wave one 32x32 MFMA tile.
+// Lane l supplies A(row = l % 32, k = k0 + 8 (l / 32) .. +7) and likewise B;
+// accumulator register r of lane l is C(8 (r / 4) + 4 (l / 32) + r % 4, l % 32).
+template <class LA, class LB, class EPI>
+__global__ __launch_bounds__(256) void gemm_nt(LA A, LB B, EPI E, uint32_t M, uint32_t N,
+                                                uint32_t K) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint32_t m0 = blockIdx.x * 64 + (wv & 1) * 32, n0 = blockIdx.y * 64 + (wv >> 1) * 32;
+  const uint32_t ra = m0 + (lane & 31), rb = n0 + (lane & 31), kh = 8 * (lane >> 5);
+  f32x16 acc = {0};
+  for (uint32_t k0 = 0; k0 < K; k0 += 16) {
+    const bf16x8 a = A.load(ra, k0 + kh);
+    const bf16x8 b = B.load(rb, k0 + kh);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const uint32_t m = m0 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4), n = n0 + (lane & 31);
+    if (m < M && n < N) E.store(m, n, acc[r]);
+  }
+}
+
+template <class LA, class LB, class EPI>
+hipError_t gemm(LA A, LB B, EPI E, uint32_t M, uint32_t N, uint32_t K, hipStream_t s) {
+  if (M == 0 || N == 0) return hipSuccess;
+  dim3 grid((M + 63) / 64, (N + 63) / 64);
+  hipLaunchKernelGGL((gemm_nt<LA, LB, EPI>), grid, dim3(256), 0, s, A, B, E, M, N, K);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ small ops
+// logit[m] = a2[m] . w3 + b3 (one wave per row, fixed-order reduction).
+__global__ void head_forward(const float* a2, const float* w3, const float* b3, uint32_t M,
+                             float* logit) {
+  const uint32_t m = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (m >= M) return;
+  float s = 0.f;
+  for (int n = lane; n < kH2; n += 64) s += a2[(uint64_t)m * kH2 + n] * w3[n];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) logit[m] = s + b3[0];
+}
+
+// BCE-with-logits with positive weight p, mean over the batch:
+// L = -(p y log s(z) + (1 - y) log(1 - s(z))), dL/dz = (s(z)(p y + 1 - y) - p y) / M.
+// dz[m]; the input gradient of layer 2 (relu-masked) in fp32, bf16 and
+// transposed bf16; the per-example loss terms.
+__global__ void head_backward(const float* logit, const float* label, uint32_t M, float pw,
+                              const float* w3, const float* a2, float* dz, float* lossv,
+                              float* dh2_f, uint16_t* dh2, uint16_t* dh2_t, uint32_t ldt) {
+  const uint32_t m = blockIdx.x;
+  if (m >= M) return;
+  const float z = logit[m], y = label[m];
+  const float sg = 1.f / (1.f + expf(-z));
+  const float g = (sg * (pw * y + 1.f - y) - pw * y) / (float)M;
+  if (threadIdx.x == 0) {
+    dz[m] = g;
+    // log s(z) = -softplus(-z), log(1 - s(z)) = -softplus(z)
+    const float sp_pos = fmaxf(z, 0.f) + log1pf(expf(-fabsf(z)));
+    const float sp_neg = sp_pos - z;
+    lossv[m] = pw * y * sp_neg + (1.f - y) * sp_pos;
+  }
+  for (uint32_t n = threadIdx.x; n < kH2; n += blockDim.x) {
+    const float d = a2[(uint64_t)m * kH2 + n] > 0.f ? g * w3[n] : 0.f;
+    dh2_f[(uint64_t)m * kH2 + n] = d;
+    const uint16_t h = to_bf16(d);
+    dh2[(uint64_t)m * kH2 + n] = h;
+    dh2_t[(uint64_t)n * ldt + m] = h;
+  }
+}
+
+// out[n] = sum_m X[m][n] (fixed order), optionally weighted by w[m].
+__global__ void colsum(const float* X, const float* w, uint32_t M, uint32_t N, float* out) {
+  const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.f;
+  for (uint32_t m = 0; m < M; ++m) s += X[(uint64_t)m * N + n] * (w ? w[m] : 1.f);
+  out[n] = s;
+}
+
+__global__ void vecsum(const float* x, uint32_t M, float* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  float s = 0.f;
+  for (uint32_t m = 0; m < M; ++m) s += x[m];
+  out[0] = s;
+}
+
+__global__ void scale(float* x, uint32_t n, float a) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] *= a;
+}
+
+// Adam with bias correction on the FP32 master parameters.
+__global__ void adam(float* p, const float* g, float* m1, float* m2, uint64_t n, float lr,
+                     float b1, float b2, float eps, float c1, float c2) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float a = b1 * m1[i] + (1.f - b1) * gi;
+  const float b = b2 * m2[i] + (1.f - b2) * gi * gi;
+  m1[i] = a;
+  m2[i] = b;
+  p[i] -= lr * (a / c1) / (sqrtf(b / c2) + eps);
+}
+
+// BF16 working copies of W1, W2 and W2 transposed.
+__global__ void refresh_bf16(const float* w1, const float* w2, uint16_t* w1b, uint16_t* w2b,
+                             uint16_t* w2tb) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (uint64_t)kH1 * kIn) w1b[i] = to_bf16(w1[i]);
+  if (i < (uint64_t)kH2 * kH1) {
+    const uint32_t n = (uint32_t)(i / kH1), k = (uint32_t)(i % kH1);
+    const uint16_t h = to_bf16(w2[i]);
+    w2b[i] = h;
+    w2tb[(uint64_t)k * kH2 + n] = h;
+  }
+}
+
+inline uint32_t blocks(uint64_t n, uint32_t t = 256) { return (uint32_t)((n + t - 1) / t); }
+
+}  // namespace mlp
+
+using namespace mlp;
+
+hipError_t mlp_refresh(MlpState& S, hipStream_t s) {
+  hipLaunchKernelGGL(refresh_bf16, dim3(blocks((uint64_t)kH1 * kIn)), dim3(256), 0, s,
+                     S.params + kOffW1, S.params + kOffW2, S.w1b, S.w2b, S.w2tb);
+  return hipGetLastError();
+}
+
+// Forward of M pairs (M <= S.max_batch); with `train`, also the transposed
+// layer-1 activations the weight gradient needs.
+hipError_t mlp_forward(MlpState& S, const uint64_t* sig, const uint64_t* pairs, uint32_t M,
+                       float* logit, bool train, hipStream_t s) {
+  hipError_t e;
+  PairRows X{sig, pairs, M};
+  Dense W1{S.w1b, kIn, kH1};
+  EpiHidden E1{S.params + kOffB1, S.a1, train ? S.a1t : nullptr, nullptr, kH1, S.max_batch};
+  if ((e = gemm(X, W1, E1, M, kH1, kIn, s))) return e;
+  Dense A1{S.a1, kH1, M};
+  Dense W2{S.w2b, kH1, kH2};
+  EpiHidden E2{S.params + kOffB2, S.a2b, nullptr, S.a2, kH2, 0};
+  if ((e = gemm(A1, W2, E2, M, kH2, kH1, s))) return e;
+  hipLaunchKernelGGL(head_forward, dim3(blocks(M, 4)), dim3(256), 0, s, S.a2,
+                     S.params + kOffW3, S.params + kOffB3, M, logit);
+  return hipGetLastError();
+}
+
+// Loss and all parameter gradients of one batch into S.grads (no update).
+hipError_t mlp_backward(MlpState& S, const uint64_t* sig, const uint64_t* pairs,
+                        const float* label, uint32_t M, float pos_weight, float* loss,
+                        hipStream_t s) {
+  hipError_t e;
+  if ((e = mlp_forward(S, sig, pairs, M, S.logit, true, s))) return e;
+  float* G = S.grads;
+  hipLaunchKernelGGL(head_backward, dim3(M), dim3(256), 0, s, S.logit, label, M, pos_weight,
+                     S.params + kOffW3, S.a2, S.dz, S.lossv, S.dh2f, S.dh2, S.dh2t, S.max_batch);
+  // head: dw3 = a2^T dz, db3 = sum dz, loss = sum of terms / M
+  hipLaunchKernelGGL(colsum, dim3(blocks(kH2)), dim3(256), 0, s, S.a2, S.dz, M, kH2, G + kOffW3);
+  hipLaunchKernelGGL(vecsum, dim3(1), dim3(64), 0, s, S.dz, M, G + kOffB3);
+  hipLaunchKernelGGL(vecsum, dim3(1), dim3(64), 0, s, S.lossv, M, loss);
+  hipLaunchKernelGGL(scale, dim3(1), dim3(64), 0, s, loss, 1u, 1.f / (float)M);
+  // layer 2: db2 = colsum dh2, dW2[n][k] = sum_m dh2[m][n] a1[m][k]
+  hipLaunchKernelGGL(colsum, dim3(blocks(kH2)), dim3(256), 0, s, S.dh2f, nullptr, M, kH2,
+                     G + kOffB2);
+  {
+    Dense A{S.dh2t, S.max_batch, kH2};
+    Dense B{S.a1t, S.max_batch, kH1};
+    EpiStore E{G + kOffW2, kH1};
+    if ((e = gemm(A, B, E, kH2, kH1, M, s))) return e;
+  }
+  // layer 1 input gradient: dA1[m][k] = sum_n dh2[m][n] W2[n][k], relu mask
+  {
+    Dense A{S.dh2, kH2, M};
+    Dense B{S.w2tb, kH2, kH1};
+    EpiReluGrad E{S.a1, S.dh1f, S.dh1t, kH1, S.max_batch};
+    if ((e = gemm(A, B, E, M, kH1, kH2, s))) return e;
+  }
+  hipLaunchKernelGGL(colsum, dim3(blocks(kH1)), dim3(256), 0, s, S.dh1f, nullptr, M, kH1,
+                     G + kOffB1);
+  // dW1[n][f] = sum_m dh1[m][n] x[m][f]
+  {
+    Dense A{S.dh1t, S.max_batch, kH1};
+    PairCols B{sig, pairs, M};
+    EpiStore E{G + kOffW1, kIn};
+    if ((e = gemm(A, B, E, kH1, kIn, M, s))) return e;
+  }
+  return hipGetLastError();
+}
+
+hipError_t mlp_adam(MlpState& S, float lr, float b1, float b2, float eps, hipStream_t s) {
+  S.step += 1;
+  const float c1 = 1.f - powf(b1, (float)S.step), c2 = 1.f - powf(b2, (float)S.step);
+  hipLaunchKernelGGL(adam, dim3(blocks(kParams)), dim3(256), 0, s, S.params, S.grads, S.m1, S.m2,
+                     (uint64_t)kParams, lr, b1, b2, eps, c1, c2);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  return mlp_refresh(S, s);
+}
+
+}  // namespace kripke

@@ -471,3 +471,30 @@ def retrieval_corpus(seed: int, count: int = 10000, n_words: int = 2000, max_len
         seen.add(t)
         out.append(f)
     return out
+
+
+# ------------------------------------------------------- signature samples
+def signature_samples(seed: int = SEED_C5_TEST, n3: int = 3520) -> np.ndarray:
+    """4,096 pointed models (n, frame, valuation, world) over 2 variables, packed
+    n << 60 | frame << 24 | val << 4 | world, in aligned groups of 64 with one n:
+    n3 distinct three-world models drawn without replacement (seeded), all 512
+    two-world models, and the 8 one-world models each repeated 8 times."""
+    assert n3 % 64 == 0 and n3 + 512 + 64 == 4096
+    rng = SplitMix64(seed, 3)
+    universe = 512 * 64 * 3  # three-world (frame, valuation, world) triples
+    chosen: set[int] = set()
+    order: list[int] = []
+    while len(order) < n3:
+        x = rng.below(universe)
+        if x not in chosen:
+            chosen.add(x)
+            order.append(x)
+
+    def pack1(n, f, v, w):
+        return (n << 60) | (f << 24) | (v << 4) | w
+
+    out = [pack1(3, x // 192, (x // 3) % 64, x % 3) for x in order]
+    out += [pack1(2, f, v, w) for f in range(16) for v in range(16) for w in range(2)]
+    one = [pack1(1, f, v, 0) for f in range(2) for v in range(4)]
+    out += [one[i % 8] for i in range(64)]
+    return np.array(out, dtype=np.uint64)

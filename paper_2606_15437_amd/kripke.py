@@ -52,6 +52,18 @@ def lib():
             "kripke_version": [],
             "kripke_program_stats": [u8p, u32p, u32, u32, C.POINTER(C.c_int32)],
             "kripke_calibrate_int32": [C.POINTER(C.c_double), vp],
+            "kripke_signatures": [u8p, u32p, u32, u32, u64p, u32, vp, vp],
+            "kripke_knn_pairs": [vp, u32, u32, u32, vp, vp, vp],
+            "kripke_pair_hamming": [vp, u32, vp, u64, vp, vp],
+            "kripke_select_top": [vp, u64, u64, vp, vp],
+            "kripke_mlp_create": [u64, u32, C.POINTER(vp)],
+            "kripke_mlp_destroy": [vp],
+            "kripke_mlp_get_params": [vp, C.POINTER(C.c_float)],
+            "kripke_mlp_set_params": [vp, C.POINTER(C.c_float)],
+            "kripke_mlp_get_grads": [vp, C.POINTER(C.c_float)],
+            "kripke_mlp_forward": [vp, vp, u32, vp, u64, vp, vp],
+            "kripke_mlp_gradients": [vp, vp, u32, vp, vp, u32, C.c_float, vp, vp],
+            "kripke_mlp_adam_step": [vp, C.c_float, C.c_float, C.c_float, C.c_float, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -180,6 +192,94 @@ def kripke_calibrate_int32(stream=None):
     r = C.c_double()
     _check(lib().kripke_calibrate_int32(C.byref(r), _stream(stream)))
     return r.value
+
+
+MLP_PARAMS = 4326401
+MLP_SHAPES = (("W1", (512, 8192)), ("b1", (512,)), ("W2", (256, 512)), ("b2", (256,)),
+              ("w3", (256,)), ("b3", (1,)))
+
+
+def kripke_signatures(code, offsets, nvars, samples, d_sig, stream=None):
+    """d_sig: CUDA int64 tensor [B][nsamples/64]; samples: host uint64 packed models."""
+    c, cp = _host_u8(code)
+    o, op = _host_u32(offsets)
+    smp = np.ascontiguousarray(np.asarray(samples, dtype=np.uint64))
+    _check(lib().kripke_signatures(cp, op, len(o) - 1, nvars,
+                                   smp.ctypes.data_as(C.POINTER(C.c_uint64)), len(smp),
+                                   _ptr(d_sig), _stream(stream)))
+
+
+def kripke_knn_pairs(d_sig, k, d_pairs, d_npairs, stream=None):
+    nf, words = d_sig.shape
+    _check(lib().kripke_knn_pairs(_ptr(d_sig), nf, words, k, _ptr(d_pairs), _ptr(d_npairs),
+                                  _stream(stream)))
+
+
+def kripke_pair_hamming(d_sig, d_pairs, npairs, d_dist, stream=None):
+    _check(lib().kripke_pair_hamming(_ptr(d_sig), d_sig.shape[1], _ptr(d_pairs), npairs,
+                                     _ptr(d_dist), _stream(stream)))
+
+
+def kripke_select_top(d_scores, budget, d_idx, stream=None):
+    _check(lib().kripke_select_top(_ptr(d_scores), d_scores.numel(), budget, _ptr(d_idx),
+                                   _stream(stream)))
+
+
+def kripke_mlp_create(seed, max_batch):
+    h = C.c_void_p()
+    _check(lib().kripke_mlp_create(seed, max_batch, C.byref(h)))
+    return h
+
+
+def kripke_mlp_destroy(h):
+    _check(lib().kripke_mlp_destroy(h))
+
+
+def _fbuf(n):
+    a = np.zeros(n, dtype=np.float32)
+    return a, a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def kripke_mlp_get_params(h):
+    a, p = _fbuf(MLP_PARAMS)
+    _check(lib().kripke_mlp_get_params(h, p))
+    return a
+
+
+def kripke_mlp_set_params(h, params):
+    a = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+    assert a.size == MLP_PARAMS
+    _check(lib().kripke_mlp_set_params(h, a.ctypes.data_as(C.POINTER(C.c_float))))
+
+
+def kripke_mlp_get_grads(h):
+    a, p = _fbuf(MLP_PARAMS)
+    _check(lib().kripke_mlp_get_grads(h, p))
+    return a
+
+
+def kripke_mlp_forward(h, d_sig, d_pairs, d_logits, stream=None):
+    _check(lib().kripke_mlp_forward(h, _ptr(d_sig), d_sig.shape[1], _ptr(d_pairs), d_pairs.numel(),
+                                    _ptr(d_logits), _stream(stream)))
+
+
+def kripke_mlp_gradients(h, d_sig, d_pairs, d_labels, pos_weight, d_loss, stream=None):
+    _check(lib().kripke_mlp_gradients(h, _ptr(d_sig), d_sig.shape[1], _ptr(d_pairs), _ptr(d_labels),
+                                      d_pairs.numel(), pos_weight, _ptr(d_loss), _stream(stream)))
+
+
+def kripke_mlp_adam_step(h, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().kripke_mlp_adam_step(h, lr, beta1, beta2, eps, _stream(stream)))
+
+
+def split_params(flat):
+    """Named views of the flat FP32 parameter (or gradient) vector."""
+    out, at = {}, 0
+    for name, shape in MLP_SHAPES:
+        n = int(np.prod(shape))
+        out[name] = flat[at:at + n].reshape(shape)
+        at += n
+    return out
 
 
 # ---------------------------------------------------------------- helpers

@@ -1,0 +1,197 @@
+"""GPU tests of the learned-proposal path: signatures against the oracle, candidate
+pairs and rankings against brute force written here, and the MFMA MLP against the CPU
+reference (forward, gradients, Adam) plus a training sanity check."""
+import numpy as np
+import pytest
+
+from paper_2606_15437_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_15437_amd import kripke
+    kripke.lib()
+    return kripke
+
+
+def _sig_gpu(kr, formulas, samples):
+    import torch
+    code, offs = I.pack(formulas)
+    d = torch.zeros((len(formulas), len(samples) // 64), dtype=torch.int64, device="cuda")
+    kr.kripke_signatures(code, offs, 2, samples, d)
+    torch.cuda.synchronize()
+    return kr.as_u64(d)
+
+
+def test_signatures_match_oracle(kr, orc):
+    samples = I.signature_samples()
+    fs = I.retrieval_corpus(I.SEED_C5_TEST, 300, n_words=120)
+    got = _sig_gpu(kr, fs, samples)
+    exp = orc.signatures(fs, samples, 2)
+    assert (got == exp).all()
+
+
+def test_signatures_reject_mixed_groups(kr):
+    import torch
+    samples = I.signature_samples().copy()
+    samples[5] = (2 << 60) | (1 << 24) | (0 << 4) | 0  # a 2-world model inside a 3-world group
+    code, offs = I.pack([[I.TOP]])
+    d = torch.zeros((1, 64), dtype=torch.int64, device="cuda")
+    with pytest.raises(kr.KripkeError):
+        kr.kripke_signatures(code, offs, 2, samples, d)
+
+
+def _brute_knn_pairs(sig, k):
+    nf = len(sig)
+    d = np.zeros((nf, nf), dtype=np.int64)
+    for i in range(nf):
+        x = sig[i] ^ sig
+        d[i] = np.unpackbits(x.view(np.uint8), axis=1).sum(1)
+    pairs = set()
+    for i in range(nf):
+        order = sorted((int(d[i, j]), j) for j in range(nf) if j != i)[:k]
+        for _, j in order:
+            pairs.add((min(i, j), max(i, j)))
+    return sorted(pairs), d
+
+
+def test_knn_pairs_and_hamming(kr):
+    import torch
+    rng = np.random.default_rng(11)
+    nf, k = 300, 17
+    # clustered signatures so that ties and asymmetric neighbourhoods occur
+    base = rng.integers(0, 2 ** 63, size=(20, 64), dtype=np.uint64)
+    sig = base[rng.integers(0, 20, size=nf)].copy()
+    flips = rng.integers(0, 4096, size=(nf, 3))
+    for i in range(nf):
+        for b in flips[i]:
+            sig[i, b // 64] ^= np.uint64(1) << np.uint64(b % 64)
+    d_sig = torch.as_tensor(sig.view(np.int64), device="cuda")
+    d_pairs = torch.zeros(nf * k, dtype=torch.int64, device="cuda")
+    d_n = torch.zeros(1, dtype=torch.int64, device="cuda")
+    kr.kripke_knn_pairs(d_sig, k, d_pairs, d_n)
+    torch.cuda.synchronize()
+    npairs = int(d_n.item())
+    got = kr.as_u64(d_pairs)[:npairs]
+    exp, dist = _brute_knn_pairs(sig, k)
+    assert [(int(p >> 32), int(p & 0xFFFFFFFF)) for p in got] == exp
+    d_dist = torch.zeros(npairs, dtype=torch.int32, device="cuda")
+    kr.kripke_pair_hamming(d_sig, d_pairs, npairs, d_dist)
+    torch.cuda.synchronize()
+    assert list(d_dist.cpu().numpy()) == [int(dist[i, j]) for i, j in exp]
+
+
+def test_select_top_stable(kr):
+    import torch
+    rng = np.random.default_rng(5)
+    s = rng.integers(-20, 20, size=5000).astype(np.float32) / 4
+    s[::7] = 0.0
+    s[3::11] = -0.0
+    d_s = torch.as_tensor(s, device="cuda")
+    d_i = torch.zeros(1000, dtype=torch.int64, device="cuda")
+    kr.kripke_select_top(d_s, 1000, d_i)
+    torch.cuda.synchronize()
+    exp = sorted(range(len(s)), key=lambda i: (-float(s[i]) if s[i] != 0 else 0.0, i))[:1000]
+    assert list(d_i.cpu().numpy()) == exp
+
+
+# ----------------------------------------------------------------- MLP
+def _mlp_problem(kr, M=128, seed=9):
+    import torch
+    rng = np.random.default_rng(seed)
+    sig = rng.integers(0, 2 ** 63, size=(40, 64), dtype=np.uint64)
+    ij = rng.integers(0, 40, size=(M, 2))
+    pairs = np.array([(int(i) << 32) | int(j) for i, j in ij], dtype=np.uint64)
+    y = (rng.random(M) < 0.3).astype(np.float32)
+    d_sig = torch.as_tensor(sig.view(np.int64), device="cuda")
+    d_pairs = torch.as_tensor(pairs.view(np.int64), device="cuda")
+    d_y = torch.as_tensor(y, device="cuda")
+    return sig, pairs, y, d_sig, d_pairs, d_y
+
+
+def _close(got, exp, rel):
+    scale = max(float(np.max(np.abs(exp))), 1e-12)
+    return float(np.max(np.abs(got - exp))) <= rel * scale
+
+
+def test_mlp_forward_matches_reference(kr):
+    import torch
+    from oracle import mlp_ref as R
+    sig, pairs, y, d_sig, d_pairs, d_y = _mlp_problem(kr, M=200)
+    h = kr.kripke_mlp_create(1234, 128)
+    try:
+        # non-zero biases so every term of the epilogues is exercised
+        p = kr.kripke_mlp_get_params(h)
+        rng = np.random.default_rng(1)
+        named = kr.split_params(p)
+        for b in ("b1", "b2", "b3"):
+            named[b][:] = rng.normal(0, 0.05, named[b].shape)
+        kr.kripke_mlp_set_params(h, p)
+        d_z = torch.zeros(len(pairs), dtype=torch.float32, device="cuda")
+        kr.kripke_mlp_forward(h, d_sig, d_pairs, d_z)  # 200 pairs: two chunks of <= 128
+        torch.cuda.synchronize()
+        ref = R.forward(R.unflatten(p), R.pair_inputs(sig, pairs))["z"]
+        assert _close(d_z.cpu().numpy(), ref, 1e-2)
+    finally:
+        kr.kripke_mlp_destroy(h)
+
+
+def test_mlp_gradients_and_adam_match_reference(kr):
+    import torch
+    from oracle import mlp_ref as R
+    sig, pairs, y, d_sig, d_pairs, d_y = _mlp_problem(kr, M=128)
+    h = kr.kripke_mlp_create(77, 256)
+    try:
+        p = kr.kripke_mlp_get_params(h)
+        d_loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        kr.kripke_mlp_gradients(h, d_sig, d_pairs, d_y, 2.5, d_loss)
+        torch.cuda.synchronize()
+        g = kr.split_params(kr.kripke_mlp_get_grads(h))
+        X = R.pair_inputs(sig, pairs)
+        loss, gr, _ = R.loss_and_grads(R.unflatten(p), X, y.astype(np.float64), 2.5, bf16_on=True)
+        assert abs(float(d_loss.item()) - loss) <= 1e-4 * max(1.0, abs(loss))
+        for name in ("W1", "b1", "W2", "b2", "w3", "b3"):
+            assert _close(g[name], gr[name], 2e-2), name
+        # one Adam step from the GPU's own gradients equals the reference step
+        gflat = kr.kripke_mlp_get_grads(h).astype(np.float64)
+        kr.kripke_mlp_adam_step(h, lr=1e-3)
+        torch.cuda.synchronize()
+        q = kr.kripke_mlp_get_params(h)
+        qr, _, _ = R.adam(p.astype(np.float64), gflat, np.zeros_like(gflat), np.zeros_like(gflat), 1,
+                          lr=1e-3)
+        assert np.max(np.abs(q - qr)) <= 1e-6
+    finally:
+        kr.kripke_mlp_destroy(h)
+
+
+def test_mlp_training_reduces_loss(kr):
+    """A learnable task: label = 1 iff the XOR half of the input is empty in the first word
+    (pairs equal there).  Twenty Adam steps must cut the loss substantially."""
+    import torch
+    rng = np.random.default_rng(3)
+    sig = rng.integers(0, 2 ** 63, size=(64, 64), dtype=np.uint64)
+    sig[32:, 0] = sig[:32, 0]
+    ij = rng.integers(0, 64, size=(512, 2))
+    ij[::2, 1] = (ij[::2, 0] + 32) % 64
+    pairs = np.array([(int(i) << 32) | int(j) for i, j in ij], dtype=np.uint64)
+    y = np.array([float(sig[i, 0] == sig[j, 0]) for i, j in ij], dtype=np.float32)
+    d_sig = torch.as_tensor(sig.view(np.int64), device="cuda")
+    d_pairs = torch.as_tensor(pairs.view(np.int64), device="cuda")
+    d_y = torch.as_tensor(y, device="cuda")
+    d_loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    h = kr.kripke_mlp_create(5, 512)
+    try:
+        losses = []
+        for _ in range(20):
+            kr.kripke_mlp_gradients(h, d_sig, d_pairs, d_y, 1.0, d_loss)
+            kr.kripke_mlp_adam_step(h, lr=1e-3)
+            torch.cuda.synchronize()
+            losses.append(float(d_loss.item()))
+        assert losses[-1] < 0.5 * losses[0], losses
+    finally:
+        kr.kripke_mlp_destroy(h)
