@@ -291,6 +291,52 @@ def iff(phi, psi) -> list[int]:
     return list(phi) + list(psi) + [IFF]
 
 
+def _root_children(f):
+    """Postfix spans of the root's operands: [] for a leaf, [a] or [a, b]."""
+    op = f[-1]
+    if op in (NOT, BOX, DIA):
+        return [list(f[:-1])]
+    if op in (AND, OR, IMP, IFF):
+        right = _span_start(f, len(f) - 2)
+        return [list(f[:right]), list(f[right:-1])]
+    return []
+
+
+def _span_start(f, end):
+    """Start index of the subformula whose last token is f[end]."""
+    need = 1
+    k = end
+    while True:
+        op = f[k]
+        if op in (AND, OR, IMP, IFF):
+            need += 1
+        elif op in (NOT, BOX, DIA):
+            pass
+        else:
+            need -= 1
+        if need == 0:
+            return k
+        k -= 1
+
+
+def equivalent_variant(f, k: int) -> list[int]:
+    """A formula with the same truth set as f on every model, by one syntactic rewrite
+    chosen by k mod 4: double negation; swapped operands of a commutative root (else
+    double negation); modal duality at a modal root (BOX a as NOT DIA NOT a, DIA a as
+    NOT BOX NOT a; else double negation); conjunction with TOP."""
+    f = list(f)
+    r = k % 4
+    if r == 1 and f[-1] in (AND, OR, IFF):
+        a, b = _root_children(f)
+        return b + a + [f[-1]]
+    if r == 2 and f[-1] in (BOX, DIA):
+        (a,) = _root_children(f)
+        return a + [NOT, DIA if f[-1] == BOX else BOX, NOT]
+    if r == 3:
+        return f + [TOP, AND]
+    return f + [NOT, NOT]
+
+
 def alpha(m: int) -> list[int]:
     """alpha_m = (BOX DIA)^m TOP (Proposition 6, Lemma 2)."""
     return [TOP] + [DIA, BOX] * m

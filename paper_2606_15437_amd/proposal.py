@@ -1,0 +1,268 @@
+"""Learned pair proposal: rank candidate formula pairs by a trained MLP, then judge every
+proposal exactly with the census and split kernels.
+
+A *late split* (the retrieval target) is a pair (phi, psi) whose biconditional
+phi <-> psi has no countermodel on any frame with at most 4 worlds, while a
+separating model exists on the 6-8-world stress panel (Definition 2 and
+Proposition 5: the pair is k-indistinguishable for some k >= 4).  The analogue in
+the paper is representation-guided retrieval followed by exhaustive rescans
+(Section 9); here the representation is a learned scorer over exact
+small-model signatures.
+
+Steps (every evaluation runs in the library's kernels):
+  1. signatures: truth bits of each formula at 4,096 pointed models (<= 3 worlds);
+  2. universe: each formula's k nearest formulas by signature Hamming distance,
+     unordered pairs in canonical (i, j) order;
+  3. verification of a pair list: census of phi <-> psi over every frame with
+     n = 1..4 worlds and every valuation (early exit at the first
+     countermodel, survivors carried to the next n), then the first
+     separating model on the stress panel (the first frames of the seeded
+     6-, 7- and 8-world families);
+  4. labels for a separately seeded training corpus from step 3, MLP training
+     with BCE-with-logits (positive weight) and Adam;
+  5. ranking of the test universe by the MLP (learned), by canonical order
+     (plain enumeration) and by signature Hamming distance; the top `budget`
+     pairs of each are verified, and hits per 10^6 evaluated pairs reported.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import inputs as I
+from . import kripke as K
+
+NVARS = 2
+
+
+def _t():
+    import torch
+    return torch
+
+
+def signatures(formulas, samples=None, device="cuda"):
+    torch = _t()
+    samples = I.signature_samples() if samples is None else samples
+    code, offs = I.pack(formulas)
+    d = torch.zeros((len(formulas), len(samples) // 64), dtype=torch.int64, device=device)
+    K.kripke_signatures(code, offs, NVARS, samples, d)
+    return d
+
+
+def universe(d_sig, k):
+    torch = _t()
+    nf = d_sig.shape[0]
+    d_pairs = torch.zeros(nf * k, dtype=torch.int64, device=d_sig.device)
+    d_n = torch.zeros(1, dtype=torch.int64, device=d_sig.device)
+    K.kripke_knn_pairs(d_sig, k, d_pairs, d_n)
+    n = int(d_n.item())
+    return d_pairs[:n].clone()
+
+
+def stress_panel(frames_per_n=4096):
+    """The stress panel: frames 0 .. frames_per_n-1 of the seeded families at n = 6, 7, 8."""
+    return {n: I.frame_family(n, frames_per_n) for n in (6, 7, 8)}
+
+
+def _pairs_host(d_pairs):
+    p = K.as_u64(d_pairs) if hasattr(d_pairs, "is_cuda") else np.asarray(d_pairs, dtype=np.uint64)
+    return (p >> np.uint64(32)).astype(np.int64), (p & np.uint64(0xFFFFFFFF)).astype(np.int64)
+
+
+class Verifier:
+    """Exact judge of pairs: agreement through 4 worlds, then a split on the panel."""
+
+    def __init__(self, formulas, panel=None, chunk=1 << 17, log=None):
+        torch = _t()
+        self.formulas = formulas
+        self.panel = stress_panel() if panel is None else panel
+        self.d_panel = {n: torch.as_tensor(np.ascontiguousarray(fr).view(np.int32), device="cuda")
+                        for n, fr in self.panel.items()}
+        self.chunk = chunk
+        self.evals = 0.0
+        self.log = log
+        code, offs = I.pack(formulas)
+        self.code = np.concatenate([code, np.array([I.IFF], dtype=np.uint8)])
+        self.offs = offs[:-1].astype(np.int64)
+        self.lens = np.diff(offs).astype(np.int64)
+
+    def _programs(self, ia, ib, chi):
+        """CSR batch of phi_k <-> psi_k (chi=True) or of phi_0, psi_0, phi_1, ... built by
+        gathering from the packed corpus."""
+        la = self.lens[ia]
+        lb = self.lens[ib]
+        per = la + lb + (1 if chi else 0)
+        offs = np.zeros(len(ia) + 1, dtype=np.int64)
+        np.cumsum(per, out=offs[1:])
+        total = int(offs[-1])
+        pid = np.repeat(np.arange(len(ia)), per)
+        local = np.arange(total, dtype=np.int64) - offs[pid]
+        src = np.where(local < la[pid], self.offs[ia][pid] + local,
+                       np.where(local < (la + lb)[pid], self.offs[ib][pid] + local - la[pid],
+                                len(self.code) - 1))
+        code = self.code[src]
+        if chi:
+            return code, offs.astype(np.uint32)
+        split = np.empty(2 * len(ia) + 1, dtype=np.int64)
+        split[0::2] = offs
+        split[1::2] = offs[:-1] + la
+        return code, split.astype(np.uint32)
+
+    def agree_through(self, ia, ib, nmax=4):
+        """Mask of pairs whose biconditional has no countermodel on any frame with
+        n <= nmax worlds (census with early exit, survivors only per layer)."""
+        torch = _t()
+        alive = np.ones(len(ia), dtype=bool)
+        for n in range(1, nmax + 1):
+            idx = np.nonzero(alive)[0]
+            for s in range(0, len(idx), self.chunk):
+                sub = idx[s:s + self.chunk]
+                code, offs = self._programs(ia[sub], ib[sub], True)
+                out = torch.empty((len(sub), 2), dtype=torch.int64, device="cuda")
+                K.kripke_census_range(code, offs, n, K.KRIPKE_K, NVARS, 0, 1 << (n * n),
+                                      K.KRIPKE_DECIDE, out)
+                keys = K.as_u64(out)[:, 0]
+                alive[sub] = keys == K.NO_KEY
+                self.evals += float(len(sub)) * (1 << (n * n)) * (1 << (NVARS * n))
+            if self.log:
+                self.log(f"  agree n={n}: {len(idx)} in, {int(alive.sum())} agree")
+        return alive
+
+    def split_keys(self, ia, ib):
+        """First separating key on the panel (n = 6, 7, 8 in turn), or NO_KEY."""
+        torch = _t()
+        found = np.full(len(ia), K.NO_KEY, dtype=np.uint64)
+        where = np.zeros(len(ia), dtype=np.int64)
+        for n in (6, 7, 8):
+            idx = np.nonzero(found == K.NO_KEY)[0]
+            for s in range(0, len(idx), self.chunk):
+                sub = idx[s:s + self.chunk]
+                code, offs = self._programs(ia[sub], ib[sub], False)
+                out = torch.empty(len(sub), dtype=torch.int64, device="cuda")
+                K.kripke_split_batch(code, offs, self.d_panel[n], n, NVARS, out)
+                k = K.as_u64(out)
+                found[sub] = k
+                where[sub[k != K.NO_KEY]] = n
+                self.evals += float(len(sub)) * len(self.panel[n]) * (1 << (NVARS * n))
+            if self.log:
+                self.log(f"  split n={n}: {len(idx)} in, {int((where == n).sum())} split")
+        return found, where
+
+    def judge(self, d_pairs_or_host):
+        """Per pair: 1 if it is a late split (agrees through 4 worlds, splits on the panel)."""
+        ia, ib = _pairs_host(d_pairs_or_host)
+        hit = np.zeros(len(ia), dtype=bool)
+        agree = self.agree_through(ia, ib)
+        idx = np.nonzero(agree)[0]
+        keys = np.full(len(ia), K.NO_KEY, dtype=np.uint64)
+        where = np.zeros(len(ia), dtype=np.int64)
+        if len(idx):
+            k, w = self.split_keys(ia[idx], ib[idx])
+            keys[idx], where[idx] = k, w
+            hit[idx] = k != K.NO_KEY
+        return hit, {"agree4": agree, "keys": keys, "n": where}
+
+
+def train_mlp(d_sig, d_pairs, labels, steps=400, batch=512, lr=1e-3, seed=17, log=None):
+    """Train the scorer on labelled pairs (balanced sampling is left to pos_weight)."""
+    torch = _t()
+    n = d_pairs.shape[0]
+    pos = float(labels.sum())
+    pos_weight = float((n - pos) / max(pos, 1.0))
+    d_y_all = torch.as_tensor(labels.astype(np.float32), device="cuda")
+    h = K.kripke_mlp_create(seed, max(batch, 16384))
+    d_loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(seed)
+    losses = []
+    for step in range(steps):
+        sel = torch.as_tensor(rng.integers(0, n, size=batch), device="cuda")
+        K.kripke_mlp_gradients(h, d_sig, d_pairs[sel].contiguous(), d_y_all[sel].contiguous(),
+                               pos_weight, d_loss)
+        K.kripke_mlp_adam_step(h, lr=lr)
+        if step % 50 == 0 or step == steps - 1:
+            losses.append(float(d_loss.item()))
+            if log:
+                log(f"train step {step}: loss {losses[-1]:.4f}")
+    return h, losses, pos_weight
+
+
+def score(h, d_sig, d_pairs):
+    torch = _t()
+    d_z = torch.empty(d_pairs.shape[0], dtype=torch.float32, device="cuda")
+    K.kripke_mlp_forward(h, d_sig, d_pairs, d_z)
+    return d_z
+
+
+def top(d_scores, budget):
+    torch = _t()
+    b = min(budget, d_scores.numel())
+    d_idx = torch.empty(b, dtype=torch.int64, device="cuda")
+    K.kripke_select_top(d_scores, b, d_idx)
+    return d_idx
+
+
+def hamming_scores(d_sig, d_pairs):
+    torch = _t()
+    d = torch.empty(d_pairs.shape[0], dtype=torch.int32, device="cuda")
+    K.kripke_pair_hamming(d_sig, d_pairs, d_pairs.shape[0], d)
+    return -d.float()
+
+
+def run(n_test=10000, n_train=4000, k_test=None, k_train=64, budget=1_000_000, steps=400,
+        panel_frames=4096, log=print):
+    """The full protocol; returns a dict of hit counts and timings."""
+    torch = _t()
+    t0 = time.time()
+    rec = {}
+    train = I.retrieval_corpus(I.SEED_C5_TRAIN, n_train, n_words=n_train // 5)
+    test = I.retrieval_corpus(I.SEED_C5_TEST, n_test, n_words=n_test // 5)
+    panel = stress_panel(panel_frames)
+    # training labels
+    s_tr = signatures(train)
+    u_tr = universe(s_tr, k_train)
+    log(f"training universe {u_tr.shape[0]} pairs ({time.time() - t0:.1f} s)")
+    ver_tr = Verifier(train, panel, log=log)
+    lab, _ = ver_tr.judge(u_tr)
+    rec["train"] = {"formulas": n_train, "pairs": int(u_tr.shape[0]), "positives": int(lab.sum()),
+                    "label_evals": ver_tr.evals, "label_s": time.time() - t0}
+    log(f"training labels: {int(lab.sum())} late splits ({time.time() - t0:.1f} s)")
+    t1 = time.time()
+    h, losses, pw = train_mlp(s_tr, u_tr, lab, steps=steps, log=log)
+    rec["train"].update({"steps": steps, "loss": losses, "pos_weight": pw,
+                         "train_s": time.time() - t1})
+    # test universe
+    s_te = signatures(test)
+    if k_test is None:
+        k_test = max(8, min(n_test - 1, int(round(2 * 5.5e6 / n_test))))
+    u_te = universe(s_te, k_test)
+    npairs = int(u_te.shape[0])
+    rec["test"] = {"formulas": n_test, "k": k_test, "pairs": npairs, "budget": budget}
+    log(f"test universe {npairs} pairs (k={k_test})")
+    ver = Verifier(test, panel, log=log)
+    rankings = {}
+    t2 = time.time()
+    z = score(h, s_te, u_te)
+    torch.cuda.synchronize()
+    rec["test"]["score_s"] = time.time() - t2
+    rankings["learned"] = top(z, budget)
+    rankings["plain"] = torch.arange(min(budget, npairs), device="cuda")
+    rankings["hamming"] = top(hamming_scores(s_te, u_te), budget)
+    # judge the union once, then count per ranking
+    union = torch.unique(torch.cat([r for r in rankings.values()]))
+    t3 = time.time()
+    hit_u, info = ver.judge(u_te[union])
+    rec["test"]["verify_s"] = time.time() - t3
+    rec["test"]["verify_evals"] = ver.evals
+    pos_of = {int(p): i for i, p in enumerate(union.cpu().numpy())}
+    for name, r in rankings.items():
+        ids = r.cpu().numpy()
+        hits = int(sum(hit_u[pos_of[int(x)]] for x in ids))
+        rec[name] = {"evaluated": int(len(ids)), "hits": hits,
+                     "hits_per_1e6": hits * 1e6 / max(len(ids), 1)}
+        log(f"{name}: {hits} verified late splits in {len(ids)} pairs")
+    rec["hits_detail"] = {"union": int(union.numel()), "agree4": int(info["agree4"].sum()),
+                          "late_splits": int(hit_u.sum())}
+    rec["total_s"] = time.time() - t0
+    K.kripke_mlp_destroy(h)
+    return rec

@@ -68,3 +68,22 @@ def test_retrieval_corpus():
     assert len(c) == 3000 and len(set(map(tuple, c))) == 3000
     assert all(len(f) <= 21 for f in c)
     assert I.alpha(2) in c and I.alpha(3) in c
+
+
+def test_equivalent_variant_is_equivalent(orc):
+    """Each rewrite keeps the truth set: the biconditional has no countermodel on any
+    frame with at most 3 worlds, and every rewrite kind really fires."""
+    fs = I.formula_batch(0xE0F1, 120, (2, 10), (0, 3), I.LEAVES_2)
+    changed = set()
+    for k, f in enumerate(fs):
+        g = I.equivalent_variant(f, k)
+        assert g != f
+        if len(g) == len(f):
+            changed.add("swap")
+        elif g[-1] == I.NOT and len(g) == len(f) + 2 and g[-2] in (I.BOX, I.DIA):
+            changed.add("dual")
+        chi = I.iff(f, g)
+        for n in (1, 2, 3):
+            key, cnt, _ = orc.census(chi, n, 0, 2)
+            assert key == orc.NONE and cnt == 0, (I.to_text(f), I.to_text(g))
+    assert changed == {"swap", "dual"}
