@@ -35,8 +35,9 @@ struct CensusArgs {
 };
 
 // Arguments of the wave-uniform-frame kernel.  Positions are frame indices
-// (mode 0, class K) or ranks of reflexive frames (mode 1, class T); a block
-// holds 2^fast_block_log2() consecutive positions.
+// (mode 0, class K), ranks of reflexive frames (mode 1, class T) or indices
+// into a list of successor rows (mode 2); a block holds 2^fast_block_log2()
+// consecutive positions.
 struct FastArgs {
   const uint8_t* ucode;
   const uint32_t* uoff;
@@ -52,10 +53,11 @@ struct FastArgs {
   uint32_t out_stride;
   uint64_t class_stride;
   uint32_t decide;
+  const uint32_t* list_succ;    // mode 2: successor rows [positions][n]
 };
 
 bool fast_available(int n, int nvars, int ls, int mode, bool fused);
-int fast_block_log2(int n, int nvars, int ls);
+int fast_block_log2(int n, int nvars, int ls, int mode);
 hipError_t launch_fast(const FastArgs& a, int n, int nvars, int ls, int mode, bool fused, int grid,
                        hipStream_t s);
 int fast_blocks_per_cu(int n, int nvars, int ls, int mode, bool fused);

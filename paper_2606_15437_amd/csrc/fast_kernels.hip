@@ -22,6 +22,11 @@
 // mode K with `fused`, each frame also reduces into the classes T, S4 and S5
 // it belongs to (a precomputed 2-bit class level per frame), so one pass over
 // the K frames yields the census of all four classes.
+//
+// Mode LIST (split search over a caller's frame list, n * nvars >= 11): a
+// block is ONE list frame, so every relation word is wave-uniform and comes
+// from the frame's successor rows; the set bits then index valuation bits
+// 11 .. 11+LS-1 (between the lane bits and the chunk loop) instead of frames.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -60,6 +65,7 @@ __host__ __device__ constexpr int free_rank(int p) {
 
 template <int N, int MODE, int LF, int LS>
 __host__ __device__ constexpr int role(int p) {
+  if (MODE == 2) return R_UNIFORM;
   if (MODE == 1 && p % (N + 1) == 0) return R_ONE;
   const int r = free_rank<N, MODE>(p);
   return r < LF ? R_LANE : r < LF + LS ? R_SET : R_UNIFORM;
@@ -73,12 +79,14 @@ __host__ __device__ constexpr int role_idx(int p, int LF) {
 
 template <int N, int NV, int LS, int MODE>
 struct Geo {
+  static constexpr bool LIST = MODE == 2;
   static constexpr int V = N * NV;
   static constexpr int LV = V >= 11 ? 6 : (V > 5 ? V - 5 : 0);  // lane valuation bits
   static constexpr int LF = 6 - LV;                              // lane frame bits
-  static constexpr int S = 1 << LS;                              // frame sets per lane
-  static constexpr int B = LF + LS;                              // log2 frames per block
-  static constexpr int CHB = V > 11 ? V - 11 : 0;                // valuation chunk bits
+  static constexpr int S = 1 << LS;                              // sets per lane
+  static constexpr int SV = LIST ? LS : 0;                       // set bits that are valuation bits
+  static constexpr int B = LIST ? 0 : LF + LS;                   // log2 frames per block
+  static constexpr int CHB = V > 11 + SV ? V - 11 - SV : 0;      // valuation chunk bits
   static constexpr int DS = LS == 0 ? 4 : LS <= 2 ? 2 : 1;       // stack slots in registers
   static constexpr int LDS_SLOTS = 1;                            // + slots spilled to LDS
 };
@@ -121,20 +129,21 @@ __device__ __forceinline__ uint32_t rel(const Ctx<N, NV, LS, MODE>& c, int s, in
 }
 
 template <int N, int NV, int LS, int MODE>
-__device__ __forceinline__ uint32_t var_word(const Ctx<N, NV, LS, MODE>& c, int i, int w) {
+__device__ __forceinline__ uint32_t var_word(const Ctx<N, NV, LS, MODE>& c, int s, int i, int w) {
   using G = Geo<N, NV, LS, MODE>;
   const int b = i * N + w;
   if (b < 5) return c.pv[b];
   if (b < 5 + G::LV) return c.lv[b - 5];
-  return c.ch[b - 5 - G::LV];
+  if (b < 5 + G::LV + G::SV) return ((s >> (b - 5 - G::LV)) & 1) ? ~0u : 0u;
+  return c.ch[b - 5 - G::LV - G::SV];
 }
 
 template <int N, int NV, int LS, int MODE, int L>
 __device__ __forceinline__ uint32_t leaf(const Ctx<N, NV, LS, MODE>& c, int s, int w) {
   if constexpr (L < 4) {
-    return var_word(c, L, w);
+    return var_word(c, s, L, w);
   } else if constexpr (L < 8) {
-    return ~var_word(c, L - 4, w);
+    return ~var_word(c, s, L - 4, w);
   } else if constexpr (L == L_SUCC || L == L_DEAD) {
     // "has a successor": an OR over the row, seeded opaquely so it is
     // computed where used instead of being hoisted for every block
@@ -185,7 +194,7 @@ __device__ __forceinline__ uint32_t opaque_not(uint32_t x) {
 template <int N, int NV, int LS, int MODE, int L>
 __device__ __forceinline__ void f_load(Ctx<N, NV, LS, MODE>& c) {
   if constexpr (L >= 4 && L < 8) {
-    KR_FOR_SW c.acc[s][w] = opaque_not(var_word(c, L - 4, w));
+    KR_FOR_SW c.acc[s][w] = opaque_not(var_word(c, s, L - 4, w));
   } else {
     KR_FOR_SW c.acc[s][w] = leaf<N, NV, LS, MODE, L>(c, s, w);
   }
@@ -193,7 +202,7 @@ __device__ __forceinline__ void f_load(Ctx<N, NV, LS, MODE>& c) {
 template <int OP, int N, int NV, int LS, int MODE, int L>
 __device__ __forceinline__ void f_bin_leaf(Ctx<N, NV, LS, MODE>& c) {
   if constexpr (L < 8) {
-    KR_FOR_SW c.acc[s][w] = bin_lit<OP, (L >= 4)>(c.acc[s][w], var_word(c, L & 3, w));
+    KR_FOR_SW c.acc[s][w] = bin_lit<OP, (L >= 4)>(c.acc[s][w], var_word(c, s, L & 3, w));
   } else {
     KR_FOR_SW {
       const uint32_t y = leaf<N, NV, LS, MODE, L>(c, s, w);
@@ -293,7 +302,7 @@ __device__ __forceinline__ void f_modal_leaf(Ctx<N, NV, LS, MODE>& c) {
       uint32_t r = seed;
 #pragma unroll
       for (int v = 0; v < N; ++v)
-        r = modal_term<DIA, N, NV, LS, MODE, (L >= 4)>(c, s, w, v, var_word(c, L & 3, v), r);
+        r = modal_term<DIA, N, NV, LS, MODE, (L >= 4)>(c, s, w, v, var_word(c, s, L & 3, v), r);
       c.acc[s][w] = r;
     }
   }
@@ -390,9 +399,13 @@ __device__ __forceinline__ uint64_t candidate(const Ctx<N, NV, LS, MODE>& c, int
 #pragma unroll
   for (int w = N - 1; w >= 0; --w)
     if (!((c.acc[s][w] >> j) & 1u)) world = w;
-  const uint64_t pos = (blk << G::B) | ((uint64_t)s << G::LF) | (uint64_t)(lane >> G::LV);
-  const uint64_t frame = MODE == 0 ? pos : refl_frame(pos, N);
-  const uint64_t val = ((uint64_t)chunk << (5 + G::LV)) |
+  // list mode: the key's frame field is the list position, and the set is a
+  // valuation field
+  const uint64_t pos = G::LIST ? blk
+                               : (blk << G::B) | ((uint64_t)s << G::LF) | (uint64_t)(lane >> G::LV);
+  const uint64_t frame = MODE == 1 ? refl_frame(pos, N) : pos;
+  const uint64_t val = ((uint64_t)chunk << (5 + G::LV + G::SV)) |
+                       (G::LIST ? (uint64_t)s << (5 + G::LV) : 0ull) |
                        ((uint64_t)(lane & ((1 << G::LV) - 1)) << 5) | j;
   const uint64_t lk = (frame << (G::V + 4)) | (val << 4) | world;
   return readlane64(lk, fl);
@@ -402,6 +415,8 @@ template <int N, int NV, int LS, int MODE, bool FUSED>
 __global__ __launch_bounds__(256) void census_fast(FastArgs a) {
   using G = Geo<N, NV, LS, MODE>;
   static_assert(G::V >= 5, "fast kernel needs n * nvars >= 5");
+  static_assert(!G::LIST || (G::V >= 11 + LS && !FUSED),
+                "list mode needs the lane and set bits to be valuation bits");
   __shared__ uint32_t sprog[4][kMaxMicro / 4 + 4];
   __shared__ uint32_t sspill[4][G::LDS_SLOTS * G::S * N * 64];
   const int lane = threadIdx.x & 63;
@@ -439,7 +454,7 @@ __global__ __launch_bounds__(256) void census_fast(FastArgs a) {
 
     if (a.decide) {
       const uint64_t p0 = (b0 << G::B) > a.pos_begin ? (b0 << G::B) : a.pos_begin;
-      const uint64_t first_frame = MODE == 0 ? p0 : refl_frame(p0, N);
+      const uint64_t first_frame = MODE == 1 ? refl_frame(p0, N) : p0;
       uint64_t known = __hip_atomic_load(key_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       known = readlane64(known, 0);
       if (known != ~0ull && (known >> (G::V + 4)) < first_frame) continue;
@@ -468,7 +483,17 @@ __global__ __launch_bounds__(256) void census_fast(FastArgs a) {
 
     for (uint64_t blk = b0; blk < b1 && !done; ++blk) {
       const uint64_t pbase = blk << G::B;
-      const uint64_t base = MODE == 0 ? pbase : refl_frame(pbase, N);
+      uint64_t base;
+      if constexpr (G::LIST) {
+        // the list frame's successor rows, wave-uniform
+        base = 0;
+#pragma unroll
+        for (int w = 0; w < N; ++w)
+          base |= (uint64_t)__builtin_amdgcn_readfirstlane(a.list_succ[blk * N + w])
+                  << (w * N);
+      } else {
+        base = MODE == 0 ? pbase : refl_frame(pbase, N);
+      }
 #pragma unroll
       for (int w = 0; w < N; ++w)
 #pragma unroll
@@ -481,7 +506,8 @@ __global__ __launch_bounds__(256) void census_fast(FastArgs a) {
             c.ru[w][v] = 0u - (uint32_t)((base >> p) & 1u);
         }
       // valid (lane, set) pairs: positions inside [pos_begin, pos_end)
-      const bool ragged = pbase < a.pos_begin || pbase + (1ull << G::B) > a.pos_end;
+      const bool ragged =
+          !G::LIST && (pbase < a.pos_begin || pbase + (1ull << G::B) > a.pos_end);
       // class levels of the block's frames; consumed only after evaluation,
       // so the scalar load overlaps the interpreter
       uint32_t lvl_raw = 0;
@@ -545,6 +571,10 @@ __global__ __launch_bounds__(256) void census_fast(FastArgs a) {
             }
           }
         }
+        // list mode: chunks run in increasing valuation order inside one
+        // frame, so the first chunk with a failure holds the frame's least key
+        if constexpr (G::LIST)
+          if (a.decide && best[0] != ~0ull) break;
       }
 #pragma unroll
       for (int k = 0; k < NC; ++k)
@@ -624,6 +654,10 @@ const Entry kTable[] = {
     KR_E(4, 3, 1, 0, true),
     KR_E(4, 2, 1, 0, false), KR_E(4, 2, 1, 1, false), KR_E(4, 2, 1, 0, true),
     KR_E(6, 2, 0, 0, false), KR_E(6, 2, 1, 0, false), KR_E(6, 2, 1, 1, false),
+    // frame lists (split search)
+    KR_E(6, 2, 0, 2, false), KR_E(6, 2, 1, 2, false),
+    KR_E(7, 2, 0, 2, false), KR_E(7, 2, 1, 2, false), KR_E(7, 2, 2, 2, false),
+    KR_E(8, 2, 0, 2, false), KR_E(8, 2, 1, 2, false), KR_E(8, 2, 2, 2, false),
 };
 
 const Entry* find(int n, int nvars, int ls, int mode, bool fused) {
@@ -639,7 +673,8 @@ bool fast_available(int n, int nvars, int ls, int mode, bool fused) {
   return find(n, nvars, ls, mode, fused) != nullptr;
 }
 
-int fast_block_log2(int n, int nvars, int ls) {
+int fast_block_log2(int n, int nvars, int ls, int mode) {
+  if (mode == 2) return 0;
   const int V = n * nvars;
   const int lv = V >= 11 ? 6 : (V > 5 ? V - 5 : 0);
   return 6 - lv + ls;

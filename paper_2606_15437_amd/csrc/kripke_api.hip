@@ -315,7 +315,7 @@ int fast_slots(int ls) { return (ls == 0 ? 4 : ls <= 2 ? 2 : 1) + 1; }
 // Preferred number of frame sets per lane (log2) for the fast kernel, or -1
 // if no variant fits; KRIPKE_SETS_LOG2 overrides the default for tuning.
 int pick_sets(int n, int nvars, int mode, bool fused, int max_slots) {
-  static const char* env = getenv("KRIPKE_SETS_LOG2");
+  const char* env = getenv("KRIPKE_SETS_LOG2");
   std::vector<int> pref = {2, 1, 0};
   if (env) pref.insert(pref.begin(), atoi(env));
   for (int ls : pref)
@@ -360,7 +360,7 @@ bool make_tiers(const MicroBatch& mb, int n, int nvars, int mode, bool fused, in
 
 // Preferred tiering for a batch (env override, then widest variant first).
 bool pick_tiers(const MicroBatch& mb, int n, int nvars, int mode, bool fused, Tiering* t) {
-  static const char* env = getenv("KRIPKE_SETS_LOG2");
+  const char* env = getenv("KRIPKE_SETS_LOG2");
   std::vector<int> pref = {2, 1, 3, 0};
   if (env) pref.insert(pref.begin(), atoi(env));
   for (int ls : pref)
@@ -376,9 +376,12 @@ int enqueue_fast(DeviceState* ds, const DeviceBatch& db, int n, int nvars, int l
                  unsigned long long* key, unsigned long long* cnt, bool decide,
                  unsigned long long* queue, hipStream_t s, int items_per_wave = 16,
                  uint32_t init_first = 0, uint32_t order_first = 0, bool init = true,
-                 uint32_t row_formulas = 0) {
+                 uint32_t row_formulas = 0, uint32_t out_stride = 2,
+                 const uint32_t* list_succ = nullptr) {
   // row_formulas: formulas per class row of the output (the whole batch, which
-  // a tier launch covers only part of)
+  // a tier launch covers only part of); out_stride: 64-bit words between the
+  // keys of consecutive formulas (2 for census results, 1 for split keys);
+  // list_succ: the frame list of mode 2
   if (row_formulas == 0) row_formulas = nformulas;
   FastArgs a{};
   a.ucode = db.ucode;
@@ -387,7 +390,7 @@ int enqueue_fast(DeviceState* ds, const DeviceBatch& db, int n, int nvars, int l
   a.nformulas = nformulas;
   a.pos_begin = p0;
   a.pos_end = p1;
-  const int B = fast_block_log2(n, nvars, ls);
+  const int B = fast_block_log2(n, nvars, ls, mode);
   a.blk_begin = p0 >> B;
   a.nblk = p1 > p0 ? ((p1 + (1ull << B) - 1) >> B) - a.blk_begin : 0;
   const int per_cu = fast_blocks_per_cu(n, nvars, ls, mode, fused);
@@ -401,18 +404,20 @@ int enqueue_fast(DeviceState* ds, const DeviceBatch& db, int n, int nvars, int l
   a.queue = queue;
   a.out_key = key;
   a.out_cnt = cnt;
-  a.out_stride = 2;
+  a.out_stride = out_stride;
   a.class_stride = fused ? 2ull * row_formulas : 0;
   a.decide = decide;
+  a.list_succ = list_succ;
   if (fused) {
     int rc = level_table(ds, n, &a.levels);
     if (rc) return rc;
   }
   if (init)
-    KR_HIP(launch_init(key + 2ull * init_first, cnt ? cnt + 2ull * init_first : nullptr, 2,
+    KR_HIP(launch_init(key + (uint64_t)out_stride * init_first,
+                       cnt ? cnt + (uint64_t)out_stride * init_first : nullptr, out_stride,
                        fused ? 4 * nformulas : nformulas, queue, s));
   else
-    KR_HIP(launch_init(nullptr, nullptr, 2, 0, queue, s));
+    KR_HIP(launch_init(nullptr, nullptr, out_stride, 0, queue, s));
   if (a.nblk == 0 || nformulas == 0) return KRIPKE_OK;
   uint64_t grid = (uint64_t)ds->cus * per_cu;
   grid = std::min<uint64_t>(grid, std::max<uint64_t>(1, (a.total_items + 3) / 4));
@@ -425,14 +430,15 @@ int enqueue_fast(DeviceState* ds, const DeviceBatch& db, int n, int nvars, int l
 int enqueue_tiered(DeviceState* ds, const DeviceBatch& db, const Tiering& t, int n, int nvars,
                    int mode, bool fused, uint32_t nformulas, uint64_t p0, uint64_t p1,
                    unsigned long long* key, unsigned long long* cnt, bool decide,
-                   unsigned long long* queues, hipStream_t s, int ipw) {
-  KR_HIP(launch_init(key, cnt, 2, fused ? 4 * nformulas : nformulas, nullptr, s));
+                   unsigned long long* queues, hipStream_t s, int ipw, uint32_t out_stride = 2,
+                   const uint32_t* list_succ = nullptr) {
+  KR_HIP(launch_init(key, cnt, out_stride, fused ? 4 * nformulas : nformulas, nullptr, s));
   int rc = enqueue_fast(ds, db, n, nvars, t.ls_a, mode, fused, t.count_a, p0, p1, key, cnt, decide,
-                        queues, s, ipw, 0, 0, false, nformulas);
+                        queues, s, ipw, 0, 0, false, nformulas, out_stride, list_succ);
   if (rc || t.count_a == (uint32_t)t.order.size()) return rc;
   return enqueue_fast(ds, db, n, nvars, t.ls_b, mode, fused,
                       (uint32_t)t.order.size() - t.count_a, p0, p1, key, cnt, decide, queues + 1,
-                      s, ipw, 0, t.count_a, false, nformulas);
+                      s, ipw, 0, t.count_a, false, nformulas, out_stride, list_succ);
 }
 
 int upload_order(const Tiering& t, uint32_t* d_order, hipStream_t s) {
@@ -531,13 +537,27 @@ int kripke_split_batch(const uint8_t* code, const uint32_t* offsets, uint32_t np
   if ((rc = compile_batch(code, offsets, npairs, nvars, (int)n, true, &mb))) return rc;
   DeviceState* ds = nullptr;
   if ((rc = device_state(&ds))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  DeviceBatch db;
+  // wave-uniform list frames when the lanes can hold valuations only;
+  // KRIPKE_SPLIT_GENERIC=1 forces the per-lane-frame kernel (for comparison)
+  const char* force_generic = getenv("KRIPKE_SPLIT_GENERIC");
+  Tiering tiers;
+  if (!(force_generic && atoi(force_generic)) &&
+      pick_tiers(mb, (int)n, (int)nvars, 2, false, &tiers)) {
+    if ((rc = upload(mb, &db, 2, s))) return rc;
+    if ((rc = upload_order(tiers, db.order, s))) return rc;
+    rc = enqueue_tiered(ds, db, tiers, (int)n, (int)nvars, 2, false, npairs, 0, nframes,
+                        reinterpret_cast<unsigned long long*>(d_first_key), nullptr, true,
+                        db.queue, s, 16, 1, d_frames);
+    int rc2 = release(&db, s);
+    return rc ? rc : rc2;
+  }
   Scan sc;
   sc.mode = M_LIST_SUCC;
   sc.list_succ = d_frames;
   sc.pos_begin = 0;
   sc.npos = nframes;
-  hipStream_t s = (hipStream_t)stream;
-  DeviceBatch db;
   if ((rc = upload(mb, &db, 1, s))) return rc;
   rc = enqueue_scan(ds, db, sc, (int)n, (int)nvars, npairs,
                     reinterpret_cast<unsigned long long*>(d_first_key), nullptr, 1, true, true,

@@ -467,6 +467,31 @@ def frame_succ(f: int, n: int) -> list[int]:
     return [(f >> (w * n)) & ((1 << n) - 1) for w in range(n)]
 
 
+# ---------------------------------------------------------------- C4 pairs
+def config4_pool(count: int = 200_000) -> list[list[int]]:
+    """The split workload's formula pool: random 2-variable formulas, L ~ U[3,15],
+    D ~ U[0,6]."""
+    return formula_batch(SEED_C4, count, (3, 15), (0, 6), LEAVES_2, stream=1)
+
+
+def config4_designed_pairs() -> list[tuple[list[int], list[int]]]:
+    """Pairs with known late separations (Proposition 6, Lemma 2, Table 4 and the
+    pigeonhole facts): (alpha_j, alpha_k) for 2 <= j < k <= 6 and their duals, then
+    DIA^k TOP / DIA^(k+1) TOP and BOX^k BOT / BOX^(k+1) BOT for k = 4..7."""
+    out = []
+    for j in range(2, 7):
+        for k in range(j + 1, 7):
+            out.append((alpha(j), alpha(k)))
+    for j in range(2, 7):
+        for k in range(j + 1, 7):
+            out.append((alpha_dual(j), alpha_dual(k)))
+    for k in range(4, 8):
+        out.append((dia_k_top(k), dia_k_top(k + 1)))
+    for k in range(4, 8):
+        out.append((box_k_bot(k), box_k_bot(k + 1)))
+    return out
+
+
 # --------------------------------------------------------------- C5 corpus
 def modal_word_corpus(seed: int, count: int) -> list[list[int]]:
     """Modal words over {BOX, DIA, NOT} of length 0..10 on bases {p, q, T, F},

@@ -3,6 +3,8 @@
 Every comparison is on the same seeded inputs; expected values come from the
 oracle (or from facts of the paper), never from the HIP path.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -313,16 +315,48 @@ def test_tiered_fused_plan(kr):
 
 
 # ------------------------------------------------------------- split
-@pytest.mark.parametrize("n", [6, 7, 8])
-def test_split_parity_families(kr, orc, n):
-    frames = I.frame_family(n, 600)
-    fs = I.formula_batch(0x5B117, 64, (3, 12), (0, 4), I.LEAVES_2, stream=n)
+def _split_pairs(n, count=64):
+    """Random pairs (mostly split at once), designed late-splitting pairs, pairs that are
+    equivalent on every model (full scans, never split) and deep pairs (second tier)."""
+    fs = I.formula_batch(0x5B117, count, (3, 12), (0, 4), I.LEAVES_2, stream=n)
     pairs = list(zip(fs[0::2], fs[1::2]))
     pairs += [(I.alpha(1), I.alpha(2)), (I.alpha(2), I.alpha(3)), (I.alpha(3), I.alpha(4)),
               (I.dia_k_top(4), I.dia_k_top(5)), (I.box_k_bot(5), I.box_k_bot(6))]
+    pairs += [(f, I.equivalent_variant(f, k)) for k, f in enumerate(fs[:12])]
+    deep = _deep_formulas()
+    pairs += [(deep[0], deep[1]), (deep[2], I.equivalent_variant(deep[2], 1)),
+              (deep[1], I.equivalent_variant(deep[1], 3))]
+    return pairs
+
+
+def _par(fn, items):
+    """Map over host threads (the oracle's C calls release the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(fn, items))
+
+
+@pytest.mark.parametrize("n", [6, 7, 8])
+def test_split_parity_families(kr, orc, n):
+    frames = I.frame_family(n, {6: 600, 7: 600, 8: 120}[n])
+    pairs = _split_pairs(n)
     keys = kr.split(pairs, frames, n, 2)
-    for (a, b), k in zip(pairs, keys):
-        assert int(k) == orc.split(a, b, frames, 2), (I.to_text(a), I.to_text(b))
+    exp = _par(lambda ab: orc.split(ab[0], ab[1], frames, 2), pairs)
+    for (a, b), k, e in zip(pairs, keys, exp):
+        assert int(k) == e, (I.to_text(a), I.to_text(b))
+
+
+@pytest.mark.parametrize("n", [6, 7, 8])
+def test_split_list_kernel_matches_generic(kr, n, monkeypatch):
+    """The wave-uniform list kernel (default for two variables at n >= 6) and the
+    per-lane-frame kernel give identical keys on a larger panel, ragged in length."""
+    frames = I.frame_family(n, 3001, start=500)
+    pairs = _split_pairs(n, 160)
+    fast = kr.split(pairs, frames, n, 2)
+    monkeypatch.setenv("KRIPKE_SPLIT_GENERIC", "1")
+    slow = kr.split(pairs, frames, n, 2)
+    assert (fast == slow).all()
+    assert (fast == NONE).sum() >= 15 and (fast != NONE).sum() >= 60
 
 
 def test_split_designed_pins(kr):
