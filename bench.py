@@ -15,7 +15,11 @@ Also reported in the JSON line:
     bit operations of Proposition 2 on the programs actually executed (after
     exact constant folding); the figure on the source formulas is given too;
   - cpu_baseline: the CPU oracle on a bounded sample of the same workload;
-  - table1: the paper's matched single-formula workload.
+  - table1: the paper's matched single-formula workload;
+  - split: the split search (Definition 2, Proposition 5) of formula pairs that agree on
+    every model with at most 4 worlds, over the 6-, 7- and 8-world frame families;
+  - learned: the learned pair proposal at full scale (10,000-formula corpus, ~5.5M-pair
+    universe, 10^6 budget), every proposal judged exactly, against plain enumeration.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -66,6 +70,62 @@ def timed(fn, stream, reps=1):
     return e0.elapsed_time(e1) / reps
 
 
+def bench_split(args, stream):
+    """Split search over the frame families: pairs agreeing through 4 worlds (mostly never
+    separated, so nearly every frame is scanned), first separating model per pair."""
+    import torch
+    from paper_2606_15437_amd import inputs as I
+    from paper_2606_15437_amd import kripke as K
+    from paper_2606_15437_amd.split_workload import config4_pairs
+    t0 = time.time()
+    pairs, stats = config4_pairs(args.split_pairs, pool=50_000)
+    sel_s = time.time() - t0
+    code, offs = I.pack([p for ab in pairs for p in ab])
+    st = K.kripke_program_stats(*I.pack([I.iff(a, b) for a, b in pairs]), 2)
+    per = {}
+    tot_ms = tot_evals = tot_ops = 0.0
+    for n in (6, 7, 8):
+        frames = I.frame_family(n, args.split_frames)
+        d_fr = torch.as_tensor(np.ascontiguousarray(frames).view(np.int32), device="cuda")
+        out = torch.empty(len(pairs), dtype=torch.int64, device="cuda")
+        run = lambda: K.kripke_split_batch(code, offs, d_fr, n, 2, out, stream)
+        run()
+        ms = timed(run, stream)
+        keys = K.as_u64(out)
+        nval = 1 << (2 * n)
+        found = keys != K.NO_KEY
+        # frames actually scanned: up to the separating one, else all of them
+        scanned = np.where(found, (keys >> np.uint64(2 * n + 4)).astype(np.float64) + 1,
+                           float(len(frames)))
+        evals = float((scanned * nval).sum())
+        ops = float(((n * st[:, 1] + n * n * st[:, 0]) * scanned).sum()) * nval / 32.0
+        per[str(n)] = {"ms": ms, "G_evals_per_s": evals / ms / 1e6, "split": int(found.sum()),
+                       "T_int32_ops_per_s": ops / ms / 1e9}
+        tot_ms += ms
+        tot_evals += evals
+        tot_ops += ops
+        log(f"split n={n}: {ms:.0f} ms, {evals / ms / 1e6:.0f} G evals/s, "
+            f"{int(found.sum())} of {len(pairs)} pairs separated")
+    return {"workload": f"{len(pairs)} pairs agreeing through 4 worlds ({stats['designed']} "
+                        f"designed) x first {args.split_frames} frames of the n = 6, 7, 8 "
+                        f"families x all 2^(2n) valuations",
+            "G_evals_per_s": tot_evals / tot_ms / 1e6, "ms": tot_ms, "per_n": per,
+            "roofline": {"bound": "alu", "achieved": tot_ops / tot_ms / 1e9,
+                         "peak": PEAK_INT32 / 1e12, "unit": "T INT32 ops/s",
+                         "frac": tot_ops / tot_ms / 1e9 / (PEAK_INT32 / 1e12),
+                         "kernel": "census_fast<n,2,*,LIST>"},
+            "selection": dict(stats, seconds=sel_s),
+            "note": "timed per call including host compile and upload of the pair programs"}
+
+
+def bench_learned():
+    """The learned proposal protocol at full scale (every heavy step in the library)."""
+    from paper_2606_15437_amd import proposal as P
+    rec = P.run(log=log)
+    rec["train"]["loss"] = rec["train"]["loss"][-1]
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +141,10 @@ def main():
                          "HBM byte counters)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--split-pairs", type=int, default=2048)
+    ap.add_argument("--split-frames", type=int, default=65536)
+    ap.add_argument("--no-split", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -185,6 +249,9 @@ def main():
                          f"({cpu_evals:.3g} evaluations in {dt:.1f} s)"}
         log(f"cpu oracle: {cpu['value']:.4f} G evals/s on {threads} threads")
 
+    split = None if args.no_split else bench_split(args, stream)
+    learned = None if args.no_learned else bench_learned()
+
     valid = {name: int((res[c, :, 0] == K.NO_KEY).sum()) for c, name in enumerate("K T S4 S5".split())}
     rec = {
         "metric": "formula*frame*valuation G evals/s, n=5 census (batched hipGraph vs plain)",
@@ -216,6 +283,8 @@ def main():
         "cpu_baseline": cpu,
         "plain_vs_batched": plain,
         "table1": table1,
+        "split": split,
+        "learned": learned,
     }
     print(json.dumps(rec))
 

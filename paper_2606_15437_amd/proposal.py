@@ -60,6 +60,27 @@ def universe(d_sig, k):
     return d_pairs[:n].clone()
 
 
+def universe_of_size(d_sig, target):
+    """The universe for the neighbour count k whose size is closest to target (the size
+    grows with k; bisection over k)."""
+    nf = d_sig.shape[0]
+    lo, hi = 1, nf - 1
+    best = None
+    while lo <= hi:
+        k = (lo + hi) // 2
+        u = universe(d_sig, k)
+        if best is None or abs(u.shape[0] - target) < abs(best[1].shape[0] - target):
+            best = (k, u)
+        if u.shape[0] < target:
+            lo = k + 1
+        elif u.shape[0] > target:
+            hi = k - 1
+        else:
+            break
+        del u
+    return best
+
+
 def stress_panel(frames_per_n=4096):
     """The stress panel: frames 0 .. frames_per_n-1 of the seeded families at n = 6, 7, 8."""
     return {n: I.frame_family(n, frames_per_n) for n in (6, 7, 8)}
@@ -209,8 +230,8 @@ def hamming_scores(d_sig, d_pairs):
     return -d.float()
 
 
-def run(n_test=10000, n_train=4000, k_test=None, k_train=64, budget=1_000_000, steps=400,
-        panel_frames=4096, log=print):
+def run(n_test=10000, n_train=10000, universe_pairs=5_500_000, train_pairs=5_500_000,
+        budget=1_000_000, steps=2000, panel_frames=4096, log=print):
     """The full protocol; returns a dict of hit counts and timings."""
     torch = _t()
     t0 = time.time()
@@ -220,11 +241,12 @@ def run(n_test=10000, n_train=4000, k_test=None, k_train=64, budget=1_000_000, s
     panel = stress_panel(panel_frames)
     # training labels
     s_tr = signatures(train)
-    u_tr = universe(s_tr, k_train)
+    k_train, u_tr = universe_of_size(s_tr, train_pairs)
     log(f"training universe {u_tr.shape[0]} pairs ({time.time() - t0:.1f} s)")
     ver_tr = Verifier(train, panel, log=log)
     lab, _ = ver_tr.judge(u_tr)
-    rec["train"] = {"formulas": n_train, "pairs": int(u_tr.shape[0]), "positives": int(lab.sum()),
+    rec["train"] = {"formulas": n_train, "k": k_train, "pairs": int(u_tr.shape[0]),
+                    "positives": int(lab.sum()),
                     "label_evals": ver_tr.evals, "label_s": time.time() - t0}
     log(f"training labels: {int(lab.sum())} late splits ({time.time() - t0:.1f} s)")
     t1 = time.time()
@@ -233,9 +255,7 @@ def run(n_test=10000, n_train=4000, k_test=None, k_train=64, budget=1_000_000, s
                          "train_s": time.time() - t1})
     # test universe
     s_te = signatures(test)
-    if k_test is None:
-        k_test = max(8, min(n_test - 1, int(round(2 * 5.5e6 / n_test))))
-    u_te = universe(s_te, k_test)
+    k_test, u_te = universe_of_size(s_te, universe_pairs)
     npairs = int(u_te.shape[0])
     rec["test"] = {"formulas": n_test, "k": k_test, "pairs": npairs, "budget": budget}
     log(f"test universe {npairs} pairs (k={k_test})")
@@ -254,13 +274,17 @@ def run(n_test=10000, n_train=4000, k_test=None, k_train=64, budget=1_000_000, s
     hit_u, info = ver.judge(u_te[union])
     rec["test"]["verify_s"] = time.time() - t3
     rec["test"]["verify_evals"] = ver.evals
-    pos_of = {int(p): i for i, p in enumerate(union.cpu().numpy())}
+    union_h = union.cpu().numpy()  # sorted
     for name, r in rankings.items():
         ids = r.cpu().numpy()
-        hits = int(sum(hit_u[pos_of[int(x)]] for x in ids))
+        hit = hit_u[np.searchsorted(union_h, ids)]
+        hits = int(hit.sum())
+        # every ranking is stable, so a smaller budget's selection is a prefix
+        prefix = {str(b): int(hit[:b].sum()) for b in (10_000, 100_000) if b < len(ids)}
         rec[name] = {"evaluated": int(len(ids)), "hits": hits,
-                     "hits_per_1e6": hits * 1e6 / max(len(ids), 1)}
-        log(f"{name}: {hits} verified late splits in {len(ids)} pairs")
+                     "hits_per_1e6": hits * 1e6 / max(len(ids), 1), "hits_at_budget": prefix}
+        log(f"{name}: {hits} verified late splits in {len(ids)} pairs; at smaller budgets "
+            f"{prefix}")
     rec["hits_detail"] = {"union": int(union.numel()), "agree4": int(info["agree4"].sum()),
                           "late_splits": int(hit_u.sum())}
     rec["total_s"] = time.time() - t0
