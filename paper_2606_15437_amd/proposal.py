@@ -231,8 +231,10 @@ def hamming_scores(d_sig, d_pairs):
 
 
 def run(n_test=10000, n_train=10000, universe_pairs=5_500_000, train_pairs=5_500_000,
-        budget=1_000_000, steps=2000, panel_frames=4096, log=print):
-    """The full protocol; returns a dict of hit counts and timings."""
+        budget=1_000_000, steps=2000, panel_frames=4096, log=print, details=False):
+    """The full protocol; returns a dict of hit counts and timings.  With details, also
+    the judged pairs (host arrays) under "details": canonical pair codes of the verified
+    union, hit flags, agreement flags, separating keys and the n they were found at."""
     torch = _t()
     t0 = time.time()
     rec = {}
@@ -287,6 +289,11 @@ def run(n_test=10000, n_train=10000, universe_pairs=5_500_000, train_pairs=5_500
             f"{prefix}")
     rec["hits_detail"] = {"union": int(union.numel()), "agree4": int(info["agree4"].sum()),
                           "late_splits": int(hit_u.sum())}
+    if details:
+        rec["details"] = {"pairs": K.as_u64(u_te[union]).copy(), "hit": hit_u,
+                          "agree4": info["agree4"], "keys": info["keys"], "n": info["n"],
+                          "panel": panel, "rankings": {k: v.cpu().numpy()
+                                                       for k, v in rankings.items()}}
     rec["total_s"] = time.time() - t0
     K.kripke_mlp_destroy(h)
     return rec
