@@ -88,7 +88,10 @@ struct Geo {
   static constexpr int B = LIST ? 0 : LF + LS;                   // log2 frames per block
   static constexpr int CHB = V > 11 + SV ? V - 11 - SV : 0;      // valuation chunk bits
   static constexpr int DS = LS == 0 ? 4 : LS <= 2 ? 2 : 1;       // stack slots in registers
-  static constexpr int LDS_SLOTS = 1;                            // + slots spilled to LDS
+  // + slots spilled to LDS; none at LS = 3, whose 40 KB per block would cap
+  // residency at three blocks per CU (programs needing two slots run in the
+  // LS = 2 tier instead)
+  static constexpr int LDS_SLOTS = LS >= 3 ? 0 : 1;
 };
 
 // Diagonal positions whose relation bit is shared by the whole block (mode K):
@@ -270,9 +273,15 @@ __device__ __forceinline__ uint32_t modal_term(const Ctx<N, NV, LS, MODE>& c, in
 
 template <bool DIA, int N, int NV, int LS, int MODE>
 __device__ __forceinline__ void f_modal(Ctx<N, NV, LS, MODE>& c) {
+  // Every world's result reads every world's operand, so a set needs N
+  // temporaries.  The empty asm ahead of each set orders the sets, and the
+  // explicit moves retire the temporaries, so all sets share the same N
+  // registers instead of the scheduler interleaving sets and holding S * N.
 #pragma unroll
   for (int s = 0; s < Geo<N, NV, LS, MODE>::S; ++s) {
     uint32_t t[N];
+#pragma unroll
+    for (int w = 0; w < N; ++w) asm volatile("" : "+v"(c.acc[s][w]));
 #pragma unroll
     for (int w = 0; w < N; ++w) {
       uint32_t r = DIA ? 0u : ~0u;
@@ -281,7 +290,7 @@ __device__ __forceinline__ void f_modal(Ctx<N, NV, LS, MODE>& c) {
       t[w] = r;
     }
 #pragma unroll
-    for (int w = 0; w < N; ++w) c.acc[s][w] = t[w];
+    for (int w = 0; w < N; ++w) asm volatile("v_mov_b32 %0, %1" : "=v"(c.acc[s][w]) : "v"(t[w]));
   }
 }
 
@@ -418,7 +427,7 @@ __global__ __launch_bounds__(256) void census_fast(FastArgs a) {
   static_assert(!G::LIST || (G::V >= 11 + LS && !FUSED),
                 "list mode needs the lane and set bits to be valuation bits");
   __shared__ uint32_t sprog[4][kMaxMicro / 4 + 4];
-  __shared__ uint32_t sspill[4][G::LDS_SLOTS * G::S * N * 64];
+  __shared__ uint32_t sspill[4][G::LDS_SLOTS > 0 ? G::LDS_SLOTS * G::S * N * 64 : 1];
   const int lane = threadIdx.x & 63;
   uint32_t* prog = sprog[threadIdx.x >> 6];
   constexpr int NC = FUSED ? 4 : 1;

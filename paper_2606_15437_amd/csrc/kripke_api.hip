@@ -309,8 +309,8 @@ int enqueue_scan(DeviceState* ds, const DeviceBatch& db, const Scan& sc, int n, 
 }
 
 // Stack slots of the fast kernel variant with 2^ls frame sets per lane:
-// register slots plus one LDS overflow slot.
-int fast_slots(int ls) { return (ls == 0 ? 4 : ls <= 2 ? 2 : 1) + 1; }
+// register slots plus one LDS overflow slot below ls = 3.
+int fast_slots(int ls) { return ls == 0 ? 5 : ls <= 2 ? 3 : 1; }
 
 // Preferred number of frame sets per lane (log2) for the fast kernel, or -1
 // if no variant fits; KRIPKE_SETS_LOG2 overrides the default for tuning.
