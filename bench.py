@@ -19,7 +19,9 @@ Also reported in the JSON line:
   - split: the split search (Definition 2, Proposition 5) of formula pairs that agree on
     every model with at most 4 worlds, over the 6-, 7- and 8-world frame families;
   - learned: the learned pair proposal at full scale (10,000-formula corpus, ~5.5M-pair
-    universe, 10^6 budget), every proposal judged exactly, against plain enumeration.
+    universe, 10^6 budget), every proposal judged exactly, against plain enumeration;
+  - census_reproduction: the paper's five-world census (Section 6): 44,678 enumerated
+    formulas -> 5,621 classes -> 5,624 formulas x K/T/S4/S5 x every frame n <= 5.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -129,6 +131,17 @@ def bench_learned():
     return rec
 
 
+def bench_reproduction():
+    """The five-world census of Section 6 (paper: 1.63e14 evaluations in 45 minutes)."""
+    from paper_2606_15437_amd import census_corpus as C
+    out, _, _ = C.run(log=log)
+    out["G_evals_per_s_five_world"] = out["k_frame_evals"] / out["census_seconds"] / 1e9
+    out["paper"] = {"raw_trees": 44678, "classes": 5621, "formulas": 5624,
+                    "K_refuted_on_1": 5086, "K_refuted_on_2": 536, "K_survivors": 2,
+                    "T->S4": 48, "S4->S5": 118, "minutes": 45, "evals": 1.63e14}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +161,7 @@ def main():
     ap.add_argument("--split-frames", type=int, default=65536)
     ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-reproduction", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -254,6 +268,7 @@ def main():
 
     split = None if args.no_split else bench_split(args, stream)
     learned = None if args.no_learned else bench_learned()
+    reproduction = None if args.no_reproduction else bench_reproduction()
 
     valid = {name: int((res[c, :, 0] == K.NO_KEY).sum()) for c, name in enumerate("K T S4 S5".split())}
     rec = {
@@ -288,6 +303,7 @@ def main():
         "table1": table1,
         "split": split,
         "learned": learned,
+        "census_reproduction": reproduction,
     }
     print(json.dumps(rec))
 

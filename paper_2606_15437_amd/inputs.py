@@ -467,6 +467,46 @@ def frame_succ(f: int, n: int) -> list[int]:
     return [(f >> (w * n)) & ((1 << n) - 1) for w in range(n)]
 
 
+# --------------------------------------------------- five-world census corpus
+def enumerate_formulas(max_nodes: int = 7, leaves=(VAR0, VAR0 + 1)) -> list[list[int]]:
+    """Every formula tree with at most max_nodes nodes over the given leaves, the unary
+    connectives NOT, BOX, DIA and the binary AND, OR, IMP (constant-free by default),
+    in size order; within one size: unary roots (NOT, BOX, DIA, each over the smaller
+    trees in order), then binary roots (AND, OR, IMP; left operand size ascending,
+    then left tree, then right tree).  For seven nodes over two variables this is the
+    paper's raw census enumeration (Section 6)."""
+    by_size = {1: [[x] for x in leaves]}
+    for size in range(2, max_nodes + 1):
+        out = []
+        for op in (NOT, BOX, DIA):
+            out += [t + [op] for t in by_size[size - 1]]
+        for op in (AND, OR, IMP):
+            for a in range(1, size - 1):
+                for left in by_size[a]:
+                    for right in by_size[size - 1 - a]:
+                        out.append(left + right + [op])
+        by_size[size] = out
+    return [f for size in range(1, max_nodes + 1) for f in by_size[size]]
+
+
+def named_axioms() -> list[list[int]]:
+    """The named axioms added to the census corpus: K (normality), T and D."""
+    return [parse("[](p -> q) -> ([]p -> []q)"), parse("[]p -> p"), parse("[]p -> <>p")]
+
+
+def all_pointed_models(max_n: int = 3, nvars: int = 2) -> np.ndarray:
+    """Every pointed model with at most max_n worlds, packed as for signatures
+    (n << 60 | frame << 24 | valuation << 4 | world), in aligned groups of 64 with one
+    n; a group that the models of one n do not fill repeats that n's models."""
+    out = []
+    for n in range(1, max_n + 1):
+        ms = [(n << 60) | (f << 24) | (v << 4) | w for f in range(1 << (n * n))
+              for v in range(1 << (nvars * n)) for w in range(n)]
+        pad = (-len(ms)) % 64
+        out += ms + [ms[i % len(ms)] for i in range(pad)]
+    return np.array(out, dtype=np.uint64)
+
+
 # ---------------------------------------------------------------- C4 pairs
 def config4_pool(count: int = 200_000) -> list[list[int]]:
     """The split workload's formula pool: random 2-variable formulas, L ~ U[3,15],

@@ -34,6 +34,9 @@ def lib():
     """Load libkripke.so (built by __graft_entry__.build() or paper_2606_15437_amd/build.py)."""
     global _lib
     if _lib is None:
+        # PyTorch brings its own HIP runtime; loading it first lets this library bind to
+        # the same runtime instead of starting a second one that may not see the device
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g;"
                                " g.build()'` first")

@@ -87,3 +87,20 @@ def test_equivalent_variant_is_equivalent(orc):
             key, cnt, _ = orc.census(chi, n, 0, 2)
             assert key == orc.NONE and cnt == 0, (I.to_text(f), I.to_text(g))
     assert changed == {"swap", "dual"}
+
+
+def test_census_enumeration_count():
+    """Every tree with at most seven nodes over p, q, NOT, BOX, DIA, AND, OR, IMP:
+    44,678 of them (the paper's raw census enumeration, Section 6), all distinct,
+    constant-free and in size order."""
+    fs = I.enumerate_formulas(7)
+    assert len(fs) == 44678 and len(set(map(tuple, fs))) == 44678
+    sizes = [len(f) for f in fs]
+    assert sizes == sorted(sizes) and max(sizes) == 7
+    assert all(op not in (I.TOP, I.BOT) for f in fs for op in f)
+    # counts per size follow T(1) = 2, T(s) = 3 T(s-1) + 3 sum_a T(a) T(s-1-a)
+    t = {1: 2}
+    for s in range(2, 8):
+        t[s] = 3 * t[s - 1] + 3 * sum(t[a] * t[s - 1 - a] for a in range(1, s - 1))
+    assert [sizes.count(s) for s in range(1, 8)] == [t[s] for s in range(1, 8)]
+    assert len(I.all_pointed_models(3, 2)) == 64 + 512 + 98304
