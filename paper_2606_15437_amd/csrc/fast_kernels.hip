@@ -87,7 +87,9 @@ struct Geo {
   static constexpr int SV = LIST ? LS : 0;                       // set bits that are valuation bits
   static constexpr int B = LIST ? 0 : LF + LS;                   // log2 frames per block
   static constexpr int CHB = V > 11 + SV ? V - 11 - SV : 0;      // valuation chunk bits
-  static constexpr int DS = LS == 0 ? 4 : LS <= 2 ? 2 : 1;       // stack slots in registers
+  // stack slots in registers (one at the 8-world LIST variant with four
+  // sets, which keeps it at 105 VGPRs: four waves per SIMD)
+  static constexpr int DS = LS == 0 ? 4 : (LS <= 2 && !(LIST && N >= 8 && LS == 2)) ? 2 : 1;
   // + slots spilled to LDS; none at LS = 3, whose 40 KB per block would cap
   // residency at three blocks per CU (programs needing two slots run in the
   // LS = 2 tier instead)
@@ -333,14 +335,23 @@ __device__ __forceinline__ void f_modal_leaf(Ctx<N, NV, LS, MODE>& c) {
 
 // Interpret the wave's program (staged in LDS, 8-byte padded) on the current
 // block.  Ops are consumed from a 64-bit shift register holding the next
-// eight; a zero byte means either the end of the program or an exhausted
-// register, told apart by the number of 8-byte words left.
+// eight.  Only U_END and padding are zero bytes, so an all-zero register means
+// the program ended or the register is exhausted, told apart by the number of
+// 8-byte words left; that test is one scalar compare, so the end never goes
+// through the dispatch tree.
 template <int N, int NV, int LS, int MODE>
 __device__ __forceinline__ void run(Ctx<N, NV, LS, MODE>& c, const uint32_t* prog, uint64_t first,
                                     uint32_t nwords) {
   uint64_t cur = first;
   uint32_t next = 1;
   for (;;) {
+    if (cur == 0) {
+      if (next >= nwords) return;
+      cur = ((uint64_t)__builtin_amdgcn_readfirstlane(prog[2 * next + 1]) << 32) |
+            __builtin_amdgcn_readfirstlane(prog[2 * next]);
+      ++next;
+      if ((cur & 0xffu) == 0) return;
+    }
     const uint32_t op = (uint32_t)cur & 0xffu;
     cur >>= 8;
 #define G_LOAD(L) f_load<N, NV, LS, MODE, L>(c)
@@ -354,13 +365,6 @@ __device__ __forceinline__ void run(Ctx<N, NV, LS, MODE>& c, const uint32_t* pro
 #define G_DIAL(L) f_modal_leaf<true, N, NV, LS, MODE, L>(c)
 #define G_BOXL(L) f_modal_leaf<false, N, NV, LS, MODE, L>(c)
     switch (op) {
-      case U_END:
-        if (next >= nwords) return;
-        cur = ((uint64_t)__builtin_amdgcn_readfirstlane(prog[2 * next + 1]) << 32) |
-              __builtin_amdgcn_readfirstlane(prog[2 * next]);
-        ++next;
-        if ((cur & 0xffu) == 0) return;
-        break;
       KR_L10(U_LOAD, G_LOAD)
       case U_LOAD + L_TOP: G_LOAD(L_TOP); break;
       case U_LOAD + L_BOT: G_LOAD(L_BOT); break;
@@ -450,6 +454,10 @@ __global__ __launch_bounds__(256) void census_fast(FastArgs a) {
 #pragma unroll
   for (int i = 0; i < G::LV; ++i) c.lv[i] = 0u - ((lane >> i) & 1u);
   const uint32_t lane_pos = (uint32_t)(lane >> G::LV);
+  // only the first and the last block can hold positions outside the range
+  constexpr uint64_t kBlockMask = (1ull << G::B) - 1;
+  const uint64_t rag_lo = (a.pos_begin & kBlockMask) ? (a.pos_begin >> G::B) : ~0ull;
+  const uint64_t rag_hi = (a.pos_end & kBlockMask) ? ((a.pos_end - 1) >> G::B) : ~0ull;
 
   for (;;) {
     uint64_t item = 0;
@@ -515,8 +523,7 @@ __global__ __launch_bounds__(256) void census_fast(FastArgs a) {
             c.ru[w][v] = 0u - (uint32_t)((base >> p) & 1u);
         }
       // valid (lane, set) pairs: positions inside [pos_begin, pos_end)
-      const bool ragged =
-          !G::LIST && (pbase < a.pos_begin || pbase + (1ull << G::B) > a.pos_end);
+      const bool ragged = !G::LIST && (blk == rag_lo || blk == rag_hi);
       // class levels of the block's frames; consumed only after evaluation,
       // so the scalar load overlaps the interpreter
       uint32_t lvl_raw = 0;
@@ -649,9 +656,12 @@ struct Entry {
   int n, nvars, ls, mode, fused;
   hipError_t (*launch)(const FastArgs&, int, hipStream_t);
   int (*occ)();
+  int slots;  // stack slots: registers plus LDS
 };
 
-#define KR_E(N, NV, LS, MODE, F) {N, NV, LS, MODE, F, &launch_t<N, NV, LS, MODE, F>, &occ_t<N, NV, LS, MODE, F>}
+#define KR_E(N, NV, LS, MODE, F)                                                    \
+  {N, NV, LS, MODE, F, &launch_t<N, NV, LS, MODE, F>, &occ_t<N, NV, LS, MODE, F>, \
+   Geo<N, NV, LS, MODE>::DS + Geo<N, NV, LS, MODE>::LDS_SLOTS}
 const Entry kTable[] = {
     KR_E(5, 2, 0, 0, false), KR_E(5, 2, 1, 0, false), KR_E(5, 2, 2, 0, false),
     KR_E(5, 2, 0, 0, true),  KR_E(5, 2, 1, 0, true),  KR_E(5, 2, 2, 0, true),
@@ -694,6 +704,11 @@ hipError_t launch_fast(const FastArgs& a, int n, int nvars, int ls, int mode, bo
   const Entry* e = find(n, nvars, ls, mode, fused);
   if (!e) return hipErrorInvalidValue;
   return e->launch(a, grid, s);
+}
+
+int fast_stack_slots(int n, int nvars, int ls, int mode, bool fused) {
+  const Entry* e = find(n, nvars, ls, mode, fused);
+  return e ? e->slots : 0;
 }
 
 int fast_blocks_per_cu(int n, int nvars, int ls, int mode, bool fused) {
