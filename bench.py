@@ -21,7 +21,9 @@ Also reported in the JSON line:
   - learned: the learned pair proposal at full scale (10,000-formula corpus, ~5.5M-pair
     universe, 10^6 budget), every proposal judged exactly, against plain enumeration;
   - census_reproduction: the paper's five-world census (Section 6): 44,678 enumerated
-    formulas -> 5,621 classes -> 5,624 formulas x K/T/S4/S5 x every frame n <= 5.
+    formulas -> 5,621 classes -> 5,624 formulas x K/T/S4/S5 x every frame n <= 5;
+  - active_synthesis: the 32 context-iteration pairs of Section 7, exact through five
+    worlds, template frames of six to ten worlds beyond.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -140,6 +142,16 @@ def bench_reproduction():
                     "K_refuted_on_1": 5086, "K_refuted_on_2": 536, "K_survivors": 2,
                     "T->S4": 48, "S4->S5": 118, "minutes": 45, "evals": 1.63e14}
     return out
+
+
+def bench_synthesis():
+    from paper_2606_15437_amd import synthesis as S
+    t0 = time.time()
+    recs = S.run()
+    return {"seconds": time.time() - t0, "pairs": len(recs),
+            "late_hits": sum(1 for r in recs if r["agree_through"] == 5 and r["separation"]),
+            "top": [{k: r[k] for k in ("phi", "psi", "agree_through", "separation", "R")}
+                    for r in recs[:3]]}
 
 
 def main():
@@ -269,6 +281,7 @@ def main():
     split = None if args.no_split else bench_split(args, stream)
     learned = None if args.no_learned else bench_learned()
     reproduction = None if args.no_reproduction else bench_reproduction()
+    synthesis = bench_synthesis()
 
     valid = {name: int((res[c, :, 0] == K.NO_KEY).sum()) for c, name in enumerate("K T S4 S5".split())}
     rec = {
@@ -304,6 +317,7 @@ def main():
         "split": split,
         "learned": learned,
         "census_reproduction": reproduction,
+        "active_synthesis": synthesis,
     }
     print(json.dumps(rec))
 

@@ -110,7 +110,9 @@ int kripke_census_range(const uint8_t *code, const uint32_t *offsets, uint32_t n
  * succ[w] set iff w R v), scanning positions in order, then valuations, then
  * worlds.  *d_first_key (device, 1 value) receives
  * position << (nvars*n + 4) | val << 4 | world, or KRIPKE_NO_KEY.
- * 1 <= n <= 8, nvars*n <= 24, n*... key must fit 64 bits.
+ * Limits: 1 <= n <= 10; nvars <= 4 (<= 3 for n >= 7, <= 1 for n >= 9); the
+ * key must fit 64 bits (bits for the position + nvars*n + 4 <= 64);
+ * otherwise KRIPKE_ELIMIT.
  */
 int kripke_split(const uint8_t *phi, uint32_t len_phi, const uint8_t *psi, uint32_t len_psi,
                  const uint32_t *d_frames, uint64_t nframes, uint32_t n, uint32_t nvars,

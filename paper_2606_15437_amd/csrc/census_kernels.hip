@@ -262,7 +262,7 @@ __global__ __launch_bounds__(256) void census_generic(CensusArgs a) {
       uint64_t first_frame;
       if (a.key_pos) first_frame = a.pos_begin + first_pos;
       else if (a.mode == M_RANGE_K) first_frame = a.pos_begin + first_pos;
-      else if (a.mode == M_RANGE_T) first_frame = t_frame(a.pos_begin + first_pos, N);
+      else if (a.mode == M_RANGE_T) first_frame = N * N <= 64 ? t_frame(a.pos_begin + first_pos, N) : 0;
       else first_frame = a.list_idx[a.pos_begin + first_pos];
       uint64_t known = __hip_atomic_load(key_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       known = uniform64(known);
@@ -296,7 +296,8 @@ __global__ __launch_bounds__(256) void census_generic(CensusArgs a) {
           for (int v = 0; v < N; ++v) r.R[w][v] = 0u - ((sw >> v) & 1u);
         }
         frame = p;
-      } else {
+      } else if constexpr (N * N <= 64) {
+        // frame indices exist only while the relation fits 64 bits
         if (a.mode == M_RANGE_K) frame = p;
         else if (a.mode == M_RANGE_T) frame = t_frame(p, N);
         else frame = a.list_idx[p];
@@ -514,27 +515,33 @@ static int occupancy_one() {
 using LaunchFn = hipError_t (*)(const CensusArgs&, int, hipStream_t);
 using OccFn = int (*)();
 
-static const LaunchFn kLaunch[8][5] = {KR_NV_TABLE(1), KR_NV_TABLE(2), KR_NV_TABLE(3),
-                                       KR_NV_TABLE(4), KR_NV_TABLE(5), KR_NV_TABLE(6),
-                                       {&launch_one<7, 0>, &launch_one<7, 1>, &launch_one<7, 2>,
-                                        &launch_one<7, 3>, nullptr},
-                                       {&launch_one<8, 0>, &launch_one<8, 1>, &launch_one<8, 2>,
-                                        &launch_one<8, 3>, nullptr}};
-static const OccFn kOcc[8][5] = {KR_OCC_TABLE(1), KR_OCC_TABLE(2), KR_OCC_TABLE(3),
-                                 KR_OCC_TABLE(4), KR_OCC_TABLE(5), KR_OCC_TABLE(6),
-                                 {&occupancy_one<7, 0>, &occupancy_one<7, 1>,
-                                  &occupancy_one<7, 2>, &occupancy_one<7, 3>, nullptr},
-                                 {&occupancy_one<8, 0>, &occupancy_one<8, 1>,
-                                  &occupancy_one<8, 2>, &occupancy_one<8, 3>, nullptr}};
+// 9 and 10 worlds: frame lists only, at most one variable (template frames for
+// constant and one-variable formulas)
+static const LaunchFn kLaunch[10][5] = {
+    KR_NV_TABLE(1), KR_NV_TABLE(2), KR_NV_TABLE(3), KR_NV_TABLE(4), KR_NV_TABLE(5),
+    KR_NV_TABLE(6),
+    {&launch_one<7, 0>, &launch_one<7, 1>, &launch_one<7, 2>, &launch_one<7, 3>, nullptr},
+    {&launch_one<8, 0>, &launch_one<8, 1>, &launch_one<8, 2>, &launch_one<8, 3>, nullptr},
+    {&launch_one<9, 0>, &launch_one<9, 1>, nullptr, nullptr, nullptr},
+    {&launch_one<10, 0>, &launch_one<10, 1>, nullptr, nullptr, nullptr}};
+static const OccFn kOcc[10][5] = {
+    KR_OCC_TABLE(1), KR_OCC_TABLE(2), KR_OCC_TABLE(3), KR_OCC_TABLE(4), KR_OCC_TABLE(5),
+    KR_OCC_TABLE(6),
+    {&occupancy_one<7, 0>, &occupancy_one<7, 1>, &occupancy_one<7, 2>, &occupancy_one<7, 3>,
+     nullptr},
+    {&occupancy_one<8, 0>, &occupancy_one<8, 1>, &occupancy_one<8, 2>, &occupancy_one<8, 3>,
+     nullptr},
+    {&occupancy_one<9, 0>, &occupancy_one<9, 1>, nullptr, nullptr, nullptr},
+    {&occupancy_one<10, 0>, &occupancy_one<10, 1>, nullptr, nullptr, nullptr}};
 
 hipError_t launch_census(const CensusArgs& a, int n, int nvars, int grid, hipStream_t s) {
-  if (n < 1 || n > 8 || nvars < 0 || nvars > 4 || !kLaunch[n - 1][nvars])
+  if (n < 1 || n > 10 || nvars < 0 || nvars > 4 || !kLaunch[n - 1][nvars])
     return hipErrorInvalidValue;
   return kLaunch[n - 1][nvars](a, grid, s);
 }
 
 int census_blocks_per_cu(int n, int nvars) {
-  if (n < 1 || n > 8 || nvars < 0 || nvars > 4 || !kOcc[n - 1][nvars]) return 1;
+  if (n < 1 || n > 10 || nvars < 0 || nvars > 4 || !kOcc[n - 1][nvars]) return 1;
   return kOcc[n - 1][nvars]();
 }
 

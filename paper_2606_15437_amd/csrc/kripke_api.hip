@@ -308,10 +308,6 @@ int enqueue_scan(DeviceState* ds, const DeviceBatch& db, const Scan& sc, int n, 
   return KRIPKE_OK;
 }
 
-// Stack slots of the fast kernel variant with 2^ls frame sets per lane:
-// register slots plus one LDS overflow slot below ls = 3.
-int fast_slots(int ls) { return ls == 0 ? 5 : ls <= 2 ? 3 : 1; }
-
 // Preferred number of frame sets per lane (log2) for the fast kernel, or -1
 // if no variant fits; KRIPKE_SETS_LOG2 overrides the default for tuning.
 int pick_sets(int n, int nvars, int mode, bool fused, int max_slots) {
@@ -320,7 +316,7 @@ int pick_sets(int n, int nvars, int mode, bool fused, int max_slots) {
   if (env) pref.insert(pref.begin(), atoi(env));
   for (int ls : pref)
     if (ls >= 0 && ls <= 3 && fast_available(n, nvars, ls, mode, fused) &&
-        max_slots <= fast_slots(ls))
+        max_slots <= fast_stack_slots(n, nvars, ls, mode, fused))
       return ls;
   return -1;
 }
@@ -341,10 +337,10 @@ bool make_tiers(const MicroBatch& mb, int n, int nvars, int mode, bool fused, in
   t->order.clear();
   int max_b = 0;
   for (uint32_t f : mb.order)
-    if (mb.slots[f] <= fast_slots(ls)) t->order.push_back(f);
+    if (mb.slots[f] <= fast_stack_slots(n, nvars, ls, mode, fused)) t->order.push_back(f);
   t->count_a = (uint32_t)t->order.size();
   for (uint32_t f : mb.order)
-    if (mb.slots[f] > fast_slots(ls)) {
+    if (mb.slots[f] > fast_stack_slots(n, nvars, ls, mode, fused)) {
       t->order.push_back(f);
       max_b = std::max(max_b, mb.slots[f]);
     }
@@ -352,7 +348,9 @@ bool make_tiers(const MicroBatch& mb, int n, int nvars, int mode, bool fused, in
   t->ls_b = -1;
   if (t->count_a < t->order.size()) {
     for (int l = 2; l >= 0 && t->ls_b < 0; --l)
-      if (fast_available(n, nvars, l, mode, fused) && max_b <= fast_slots(l)) t->ls_b = l;
+      if (fast_available(n, nvars, l, mode, fused) &&
+          max_b <= fast_stack_slots(n, nvars, l, mode, fused))
+        t->ls_b = l;
     if (t->ls_b < 0) return false;
   }
   return true;
@@ -526,9 +524,9 @@ int kripke_split_batch(const uint8_t* code, const uint32_t* offsets, uint32_t np
   g_err.clear();
   if (npairs == 0 || !d_first_key || (!d_frames && nframes))
     return fail(KRIPKE_EINVAL, "empty batch or null pointer");
-  if (n < 1 || n > 8) return fail(KRIPKE_ELIMIT, "split supports 1 <= n <= 8");
-  if (nvars > 4 || (n >= 7 && nvars > 3))
-    return fail(KRIPKE_ELIMIT, "split supports nvars <= 4 (<= 3 for n >= 7)");
+  if (n < 1 || n > 10) return fail(KRIPKE_ELIMIT, "split supports 1 <= n <= 10");
+  if (nvars > 4 || (n >= 7 && nvars > 3) || (n >= 9 && nvars > 1))
+    return fail(KRIPKE_ELIMIT, "split supports nvars <= 4 (<= 3 for n >= 7, <= 1 for n >= 9)");
   int posbits = 0;
   while (posbits < 64 && (1ull << posbits) < nframes) ++posbits;
   if (posbits + (int)(nvars * n) + 4 > 64) return fail(KRIPKE_ELIMIT, "key does not fit 64 bits");
