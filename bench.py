@@ -23,7 +23,9 @@ Also reported in the JSON line:
   - census_reproduction: the paper's five-world census (Section 6): 44,678 enumerated
     formulas -> 5,621 classes -> 5,624 formulas x K/T/S4/S5 x every frame n <= 5;
   - active_synthesis: the 32 context-iteration pairs of Section 7, exact through five
-    worlds, template frames of six to ten worlds beyond.
+    worlds, template frames of six to ten worlds beyond;
+  - correspondence: frame-correspondence recovery of Section 10 over the census corpus
+    (validity maps of every formula on every frame with at most four worlds).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -154,6 +156,26 @@ def bench_synthesis():
                     for r in recs[:3]]}
 
 
+def bench_correspondence():
+    import collections
+    from paper_2606_15437_amd import census_corpus as C
+    from paper_2606_15437_amd import correspondence as R
+    _, _, corpus = C.build_corpus()
+    t0 = time.time()
+    out = R.recover(corpus, max_n=4, log=log)
+    dt = time.time() - t0
+    rec = [o for o in out if isinstance(o, list) and o]
+    conds = collections.Counter(o[0] for o in rec)
+    table9 = {name: (r if r != "trivial" else "trivial")
+              for (name, _), r in zip(R.table9(), R.recover([f for _, f in R.table9()], 4))}
+    return {"formulas": len(out), "recovered": len(rec),
+            "trivial": sum(1 for o in out if o == "trivial"),
+            "unmatched": sum(1 for o in out if o == []), "seconds": dt,
+            "library_size": len(R.library()), "most_recovered": conds.most_common(8),
+            "table9": table9,
+            "paper": {"recovered": 220, "trivial": 2798, "unmatched": 2606}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -282,6 +304,7 @@ def main():
     learned = None if args.no_learned else bench_learned()
     reproduction = None if args.no_reproduction else bench_reproduction()
     synthesis = bench_synthesis()
+    correspondence = None if args.no_reproduction else bench_correspondence()
 
     valid = {name: int((res[c, :, 0] == K.NO_KEY).sum()) for c, name in enumerate("K T S4 S5".split())}
     rec = {
@@ -318,6 +341,7 @@ def main():
         "learned": learned,
         "census_reproduction": reproduction,
         "active_synthesis": synthesis,
+        "correspondence": correspondence,
     }
     print(json.dumps(rec))
 

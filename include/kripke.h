@@ -104,6 +104,18 @@ int kripke_census_range(const uint8_t *code, const uint32_t *offsets, uint32_t n
                         void *stream);
 
 /*
+ * kripke_frame_validity -- per-frame validity maps (Section 10: Val_N(phi),
+ * the set of frames on which phi holds at every world under every valuation,
+ * the input of frame-correspondence recovery).  For every formula and every
+ * frame index f in [0, 2^(n*n)) (class K), bit f % 32 of word f / 32 of row
+ * i is 1 iff formula i has no countermodel on frame f.
+ * d_bits: DEVICE uint32[nformulas][ceil(2^(n*n) / 32)], overwritten.
+ * Limits: 4 <= n <= 5, n * nvars <= 11; otherwise KRIPKE_ELIMIT.
+ */
+int kripke_frame_validity(const uint8_t *code, const uint32_t *offsets, uint32_t nformulas,
+                          uint32_t n, uint32_t nvars, uint32_t *d_bits, void *stream);
+
+/*
  * kripke_split -- first model separating phi and psi (Definition 2; by
  * Proposition 5 a countermodel of phi <-> psi) over a caller-owned device
  * frame list d_frames (uint32 succ[nframes][n], row-major, bit v of

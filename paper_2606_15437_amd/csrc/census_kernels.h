@@ -54,10 +54,13 @@ struct FastArgs {
   uint64_t class_stride;
   uint32_t decide;
   const uint32_t* list_succ;    // mode 2: successor rows [positions][n]
+  uint32_t* valid_bits;         // optional frame-validity maps [nformulas][valid_words],
+  uint64_t valid_words;         // bit p = no countermodel on position p (mode 0)
 };
 
 bool fast_available(int n, int nvars, int ls, int mode, bool fused);
 int fast_block_log2(int n, int nvars, int ls, int mode);
+int fast_stack_slots(int n, int nvars, int ls, int mode, bool fused);
 hipError_t launch_fast(const FastArgs& a, int n, int nvars, int ls, int mode, bool fused, int grid,
                        hipStream_t s);
 int fast_blocks_per_cu(int n, int nvars, int ls, int mode, bool fused);
@@ -92,6 +95,9 @@ hipError_t launch_census(const CensusArgs& a, int n, int nvars, int grid, hipStr
 int census_blocks_per_cu(int n, int nvars);
 hipError_t launch_init(unsigned long long* key, unsigned long long* cnt, uint32_t stride,
                        uint32_t count, unsigned long long* queue, hipStream_t s);
+// rows[r][0..words) = value[r] for r < nrows
+hipError_t launch_fill_rows(uint32_t* rows, uint64_t words, const uint32_t* value, uint32_t nrows,
+                            hipStream_t s);
 hipError_t launch_class_list(int n, int level, uint32_t* counts, uint64_t* total, uint64_t* list,
                              hipStream_t s);
 uint64_t t_frame_host(uint64_t j, int n);

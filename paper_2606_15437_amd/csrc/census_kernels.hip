@@ -554,6 +554,20 @@ hipError_t launch_init(unsigned long long* key, unsigned long long* cnt, uint32_
   return hipGetLastError();
 }
 
+__global__ void fill_rows(uint32_t* rows, uint64_t words, const uint32_t* value, uint32_t nrows) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < words * nrows) rows[i] = value[i / words];
+}
+
+hipError_t launch_fill_rows(uint32_t* rows, uint64_t words, const uint32_t* value, uint32_t nrows,
+                            hipStream_t s) {
+  const uint64_t total = words * nrows;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_rows, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, s, rows,
+                     words, value, nrows);
+  return hipGetLastError();
+}
+
 hipError_t launch_class_list(int n, int level, uint32_t* counts, uint64_t* total, uint64_t* list,
                              hipStream_t s) {
   const uint64_t nframes = 1ull << (n * n);

@@ -533,6 +533,9 @@ __global__ __launch_bounds__(256) void census_fast(FastArgs a) {
       uint64_t best[NC];
 #pragma unroll
       for (int k = 0; k < NC; ++k) best[k] = ~0ull;
+      // frame validity bits of the block's 2^B frames (validity maps only)
+      constexpr bool kMaps = !FUSED && !G::LIST && G::CHB == 0 && G::B <= 5;
+      uint32_t vbits = 0;
 
       for (uint32_t chunk = 0; chunk < (1u << G::CHB); ++chunk) {
 #pragma unroll
@@ -562,6 +565,19 @@ __global__ __launch_bounds__(256) void census_fast(FastArgs a) {
             if (pos < a.pos_begin || pos >= a.pos_end) fail = 0;
           }
           cnt[0] += __builtin_popcount(fail);
+          if constexpr (kMaps) {
+            if (a.valid_bits) {
+              // a frame's valuations fill 2^LV consecutive lanes: it is valid
+              // iff none of them holds a failing bit
+              const uint64_t bal = __ballot(fail != 0);
+              constexpr uint64_t kGroup = G::LV == 6 ? ~0ull : (1ull << (1 << G::LV)) - 1;
+              uint32_t inv = 0;
+#pragma unroll
+              for (int g = 0; g < (1 << G::LF); ++g)
+                if ((bal >> (g << G::LV)) & kGroup) inv |= 1u << g;
+              vbits |= (~inv & ((1u << (1 << G::LF)) - 1u)) << (s << G::LF);
+            }
+          }
           if (key[0] == ~0ull) {
             const uint64_t bal = __ballot(fail != 0);
             if (bal) {
@@ -595,6 +611,11 @@ __global__ __launch_bounds__(256) void census_fast(FastArgs a) {
 #pragma unroll
       for (int k = 0; k < NC; ++k)
         if (key[k] == ~0ull) key[k] = best[k];
+      if constexpr (kMaps) {
+        if (a.valid_bits && vbits && lane == 0)
+          atomicOr(a.valid_bits + (uint64_t)f * a.valid_words + (pbase >> 5),
+                   vbits << (uint32_t)(pbase & 31));
+      }
       if (a.decide && key[0] != ~0ull) done = true;
     }
 #pragma unroll

@@ -375,7 +375,8 @@ int enqueue_fast(DeviceState* ds, const DeviceBatch& db, int n, int nvars, int l
                  unsigned long long* queue, hipStream_t s, int items_per_wave = 16,
                  uint32_t init_first = 0, uint32_t order_first = 0, bool init = true,
                  uint32_t row_formulas = 0, uint32_t out_stride = 2,
-                 const uint32_t* list_succ = nullptr) {
+                 const uint32_t* list_succ = nullptr, uint32_t* valid_bits = nullptr,
+                 uint64_t valid_words = 0) {
   // row_formulas: formulas per class row of the output (the whole batch, which
   // a tier launch covers only part of); out_stride: 64-bit words between the
   // keys of consecutive formulas (2 for census results, 1 for split keys);
@@ -406,6 +407,8 @@ int enqueue_fast(DeviceState* ds, const DeviceBatch& db, int n, int nvars, int l
   a.class_stride = fused ? 2ull * row_formulas : 0;
   a.decide = decide;
   a.list_succ = list_succ;
+  a.valid_bits = valid_bits;
+  a.valid_words = valid_words;
   if (fused) {
     int rc = level_table(ds, n, &a.levels);
     if (rc) return rc;
@@ -429,14 +432,17 @@ int enqueue_tiered(DeviceState* ds, const DeviceBatch& db, const Tiering& t, int
                    int mode, bool fused, uint32_t nformulas, uint64_t p0, uint64_t p1,
                    unsigned long long* key, unsigned long long* cnt, bool decide,
                    unsigned long long* queues, hipStream_t s, int ipw, uint32_t out_stride = 2,
-                   const uint32_t* list_succ = nullptr) {
+                   const uint32_t* list_succ = nullptr, uint32_t* valid_bits = nullptr,
+                   uint64_t valid_words = 0) {
   KR_HIP(launch_init(key, cnt, out_stride, fused ? 4 * nformulas : nformulas, nullptr, s));
   int rc = enqueue_fast(ds, db, n, nvars, t.ls_a, mode, fused, t.count_a, p0, p1, key, cnt, decide,
-                        queues, s, ipw, 0, 0, false, nformulas, out_stride, list_succ);
+                        queues, s, ipw, 0, 0, false, nformulas, out_stride, list_succ,
+                        valid_bits, valid_words);
   if (rc || t.count_a == (uint32_t)t.order.size()) return rc;
   return enqueue_fast(ds, db, n, nvars, t.ls_b, mode, fused,
                       (uint32_t)t.order.size() - t.count_a, p0, p1, key, cnt, decide, queues + 1,
-                      s, ipw, 0, t.count_a, false, nformulas, out_stride, list_succ);
+                      s, ipw, 0, t.count_a, false, nformulas, out_stride, list_succ,
+                      valid_bits, valid_words);
 }
 
 int upload_order(const Tiering& t, uint32_t* d_order, hipStream_t s) {
@@ -507,6 +513,50 @@ int kripke_census_range(const uint8_t* code, const uint32_t* offsets, uint32_t n
   rc = enqueue_scan(ds, db, sc, (int)n, (int)nvars, nformulas, key, cnt, 2, decide,
                     false, db.queue, s);
   int rc2 = release(&db, s);
+  return rc ? rc : rc2;
+}
+
+int kripke_frame_validity(const uint8_t* code, const uint32_t* offsets, uint32_t nformulas,
+                          uint32_t n, uint32_t nvars, uint32_t* d_bits, void* stream) {
+  g_err.clear();
+  if (nformulas == 0 || !d_bits) return fail(KRIPKE_EINVAL, "empty batch or null output");
+  int rc = check_sizes(n, nvars, 5);
+  if (rc) return rc;
+  const int B0 = fast_block_log2((int)n, (int)nvars, 0, 0);
+  if (n < 4 || n * nvars > 11 || B0 > 5)
+    return fail(KRIPKE_ELIMIT, "frame validity maps need 4 <= n <= 5 and n * nvars <= 11");
+  MicroBatch mb;
+  if ((rc = compile_batch(code, offsets, nformulas, nvars, (int)n, false, &mb))) return rc;
+  Tiering tiers;
+  if (!pick_tiers(mb, (int)n, (int)nvars, 0, false, &tiers))
+    return fail(KRIPKE_ELIMIT, "no census kernel variant for this n and nvars");
+  for (int ls : {tiers.ls_a, tiers.ls_b})
+    if (ls >= 0 && fast_block_log2((int)n, (int)nvars, ls, 0) > 5)
+      return fail(KRIPKE_ELIMIT, "census kernel blocks wider than one bitmap word");
+  DeviceState* ds = nullptr;
+  if ((rc = device_state(&ds))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const uint64_t nframes = 1ull << (n * n);
+  const uint64_t words = (nframes + 31) / 32;
+  // every map starts empty; formulas that fold to TOP are valid everywhere and
+  // are skipped by the kernel, so their maps start full
+  std::vector<uint32_t> fill(nformulas);
+  for (uint32_t i = 0; i < nformulas; ++i) fill[i] = mb.is_const[i] == 1 ? ~0u : 0u;
+  uint32_t* d_fill = nullptr;
+  unsigned long long* d_res = nullptr;
+  KR_HIP(hipMallocAsync((void**)&d_fill, nformulas * 4ull, s));
+  KR_HIP(hipMallocAsync((void**)&d_res, nformulas * 16ull, s));
+  KR_HIP(hipMemcpyAsync(d_fill, fill.data(), nformulas * 4ull, hipMemcpyHostToDevice, s));
+  KR_HIP(launch_fill_rows(d_bits, words, d_fill, nformulas, s));
+  KR_HIP(hipStreamSynchronize(s));
+  DeviceBatch db;
+  if ((rc = upload(mb, &db, 2, s))) return rc;
+  if ((rc = upload_order(tiers, db.order, s))) return rc;
+  rc = enqueue_tiered(ds, db, tiers, (int)n, (int)nvars, 0, false, nformulas, 0, nframes, d_res,
+                      d_res + 1, false, db.queue, s, 16, 2, nullptr, d_bits, words);
+  int rc2 = release(&db, s);
+  KR_HIP(hipFreeAsync(d_fill, s));
+  KR_HIP(hipFreeAsync(d_res, s));
   return rc ? rc : rc2;
 }
 

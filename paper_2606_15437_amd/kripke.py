@@ -48,6 +48,7 @@ def lib():
             "kripke_census": [u8p, u32p, u32, u32, u32, u32, vp, vp],
             "kripke_census_range": [u8p, u32p, u32, u32, u32, u32, u64, u64, u32, vp, vp],
             "kripke_split": [u8p, u32, u8p, u32, vp, u64, u32, u32, vp, vp],
+            "kripke_frame_validity": [u8p, u32p, u32, u32, u32, vp, vp],
             "kripke_split_batch": [u8p, u32p, u32, vp, u64, u32, u32, vp, vp],
             "kripke_plan_create": [u8p, u32p, u32, u32, u32, u32, C.c_char_p, C.POINTER(vp)],
             "kripke_plan_launch": [vp, vp, vp],
@@ -126,6 +127,14 @@ def kripke_census_range(code, offsets, n, cls, nvars, frame_begin, frame_end, fl
     o, op = _host_u32(offsets)
     _check(lib().kripke_census_range(cp, op, len(o) - 1, n, cls, nvars, frame_begin, frame_end,
                                      flags, _ptr(d_out), _stream(stream)))
+
+
+def kripke_frame_validity(code, offsets, n, nvars, d_bits, stream=None):
+    """d_bits: CUDA int32 tensor [B, ceil(2^(n*n) / 32)], overwritten with validity maps."""
+    c, cp = _host_u8(code)
+    o, op = _host_u32(offsets)
+    _check(lib().kripke_frame_validity(cp, op, len(o) - 1, n, nvars, _ptr(d_bits),
+                                       _stream(stream)))
 
 
 def kripke_split(phi, psi, d_frames, n, nvars, d_first_key, stream=None):
