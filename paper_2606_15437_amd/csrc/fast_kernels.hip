@@ -425,7 +425,9 @@ __device__ __forceinline__ uint64_t candidate(const Ctx<N, NV, LS, MODE>& c, int
 }
 
 template <int N, int NV, int LS, int MODE, bool FUSED>
-__global__ __launch_bounds__(256) void census_fast(FastArgs a) {
+// The eight-set variants are held to 128 VGPRs: four waves per SIMD.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LS >= 3 ? 4 : 1)))
+void census_fast(FastArgs a) {
   using G = Geo<N, NV, LS, MODE>;
   static_assert(G::V >= 5, "fast kernel needs n * nvars >= 5");
   static_assert(!G::LIST || (G::V >= 11 + LS && !FUSED),
