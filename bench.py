@@ -25,7 +25,9 @@ Also reported in the JSON line:
   - active_synthesis: the 32 context-iteration pairs of Section 7, exact through five
     worlds, template frames of six to ten worlds beyond;
   - correspondence: frame-correspondence recovery of Section 10 over the census corpus
-    (validity maps of every formula on every frame with at most four worlds).
+    (validity maps of every formula on every frame with at most four worlds);
+  - adversarial: mining of context-iteration pairs, exact prefix through five worlds,
+    template frames of 6-16 worlds and six adversarial frame generators (Section 7).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -176,6 +178,18 @@ def bench_correspondence():
             "paper": {"recovered": 220, "trivial": 2798, "unmatched": 2606}}
 
 
+def bench_adversarial():
+    from paper_2606_15437_amd import adversarial as A
+    rec, _ = A.run(frames_per=16384, log=log)
+    rec["relations"] = sum(g["relations"] for g in rec["adversarial"].values())
+    rec["valuation_frame_evals"] = sum(g["valuation_frame_evals"]
+                                       for g in rec["adversarial"].values())
+    rec["paper"] = {"candidates": 476, "relations": 8995007, "valuation_frame_evals": 94.68e9,
+                    "hits_by_generator": {"erdos-renyi": 55, "edge-flip": 35, "scc-bottleneck": 0,
+                                          "dead-end": 0, "back-edge": 0, "permuted-bottleneck": 0}}
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,6 +319,7 @@ def main():
     reproduction = None if args.no_reproduction else bench_reproduction()
     synthesis = bench_synthesis()
     correspondence = None if args.no_reproduction else bench_correspondence()
+    adversarial = None if args.no_reproduction else bench_adversarial()
 
     valid = {name: int((res[c, :, 0] == K.NO_KEY).sum()) for c, name in enumerate("K T S4 S5".split())}
     rec = {
@@ -342,6 +357,7 @@ def main():
         "census_reproduction": reproduction,
         "active_synthesis": synthesis,
         "correspondence": correspondence,
+        "adversarial": adversarial,
     }
     print(json.dumps(rec))
 

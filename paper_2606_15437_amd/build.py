@@ -8,7 +8,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libkripke.so")
 OBJDIR = os.path.join(HERE, "_build")
 SOURCES = ["census_kernels.hip", "fast_kernels.hip", "calibrate.hip", "pair_kernels.hip",
-           "mlp_kernels.hip", "kripke_api.hip", "kripke_compile.cpp"]
+           "mlp_kernels.hip", "worldmask_kernels.hip", "kripke_api.hip",
+           "kripke_compile.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed-FP32 instructions are disabled for all device code.
 # The interpreters dispatch on wave-uniform opcodes; letting the structurizer

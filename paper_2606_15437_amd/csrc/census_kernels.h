@@ -92,6 +92,22 @@ hipError_t launch_pair_hamming(const uint64_t* sig, uint32_t words, const uint64
 int select_top(const float* scores, uint64_t n, uint64_t budget, uint64_t* idx, hipStream_t s);
 
 hipError_t launch_census(const CensusArgs& a, int n, int nvars, int grid, hipStream_t s);
+
+// Split search with world-set bitmasks (large frames): pair f's biconditional
+// program at ucode[uoff[f] .. uoff[f+1]), frames = successor rows [nframes][n].
+constexpr int kWorldMaskMaxN = 16;
+struct WorldMaskArgs {
+  const uint8_t* ucode;
+  const uint32_t* uoff;
+  const uint32_t* order;
+  const uint32_t* frames;
+  uint64_t nframes;
+  uint32_t n, nvars;
+  uint64_t blocks_per_item, items_per_pair, total_items;
+  unsigned long long* queue;
+  unsigned long long* out_key;  // [npairs]
+};
+hipError_t launch_split_worldmask(const WorldMaskArgs& a, int grid, hipStream_t s);
 int census_blocks_per_cu(int n, int nvars);
 hipError_t launch_init(unsigned long long* key, unsigned long long* cnt, uint32_t stride,
                        uint32_t count, unsigned long long* queue, hipStream_t s);

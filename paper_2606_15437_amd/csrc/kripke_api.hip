@@ -574,9 +574,10 @@ int kripke_split_batch(const uint8_t* code, const uint32_t* offsets, uint32_t np
   g_err.clear();
   if (npairs == 0 || !d_first_key || (!d_frames && nframes))
     return fail(KRIPKE_EINVAL, "empty batch or null pointer");
-  if (n < 1 || n > 10) return fail(KRIPKE_ELIMIT, "split supports 1 <= n <= 10");
-  if (nvars > 4 || (n >= 7 && nvars > 3) || (n >= 9 && nvars > 1))
-    return fail(KRIPKE_ELIMIT, "split supports nvars <= 4 (<= 3 for n >= 7, <= 1 for n >= 9)");
+  if (n < 1 || n > 16) return fail(KRIPKE_ELIMIT, "split supports 1 <= n <= 16");
+  if (nvars > 4 || (n >= 7 && nvars > 3) || (n >= 9 && nvars > 1 && n * nvars > 24))
+    return fail(KRIPKE_ELIMIT, "split supports nvars <= 4 (<= 3 for n >= 7) and, from 9 worlds, "
+                               "nvars * n <= 24");
   int posbits = 0;
   while (posbits < 64 && (1ull << posbits) < nframes) ++posbits;
   if (posbits + (int)(nvars * n) + 4 > 64) return fail(KRIPKE_ELIMIT, "key does not fit 64 bits");
@@ -587,6 +588,40 @@ int kripke_split_batch(const uint8_t* code, const uint32_t* offsets, uint32_t np
   if ((rc = device_state(&ds))) return rc;
   hipStream_t s = (hipStream_t)stream;
   DeviceBatch db;
+  // frames of 11..16 worlds: world-set bitmasks per lane; KRIPKE_SPLIT_WORLDMASK=1
+  // selects that kernel at any size (for comparison)
+  const char* force_wm = getenv("KRIPKE_SPLIT_WORLDMASK");
+  if (n > 10 || (n >= 9 && nvars >= 2) || (force_wm && atoi(force_wm))) {
+    if (nvars * n > 24) return fail(KRIPKE_ELIMIT, "world-mask split needs nvars * n <= 24");
+    if ((rc = upload(mb, &db, 1, s))) return rc;
+    WorldMaskArgs a{};
+    a.ucode = db.ucode;
+    a.uoff = db.uoff;
+    a.order = db.order;
+    a.frames = d_frames;
+    a.nframes = nframes;
+    a.n = n;
+    a.nvars = nvars;
+    const uint64_t units = nframes << (nvars * n);
+    const uint64_t nblocks = (units + 63) / 64;
+    const uint64_t waves = (uint64_t)ds->cus * 16;
+    uint64_t bpi = std::max<uint64_t>(1, (nblocks * npairs + 16 * waves - 1) / (16 * waves));
+    bpi = std::min<uint64_t>(bpi, 1ull << 16);
+    a.blocks_per_item = bpi;
+    a.items_per_pair = (nblocks + bpi - 1) / bpi;
+    a.total_items = a.items_per_pair * npairs;
+    a.queue = db.queue;
+    a.out_key = reinterpret_cast<unsigned long long*>(d_first_key);
+    rc = KRIPKE_OK;
+    hipError_t e = launch_init(a.out_key, nullptr, 1, npairs, db.queue, s);
+    if (e == hipSuccess && a.total_items) {
+      const uint64_t grid = std::min<uint64_t>((uint64_t)ds->cus * 4, (a.total_items + 3) / 4);
+      e = launch_split_worldmask(a, (int)std::max<uint64_t>(grid, 1), s);
+    }
+    if (e != hipSuccess) rc = fail(KRIPKE_EHIP, std::string("world-mask split: ") + hipGetErrorString(e));
+    int rc2 = release(&db, s);
+    return rc ? rc : rc2;
+  }
   // wave-uniform list frames when the lanes can hold valuations only;
   // KRIPKE_SPLIT_GENERIC=1 forces the per-lane-frame kernel (for comparison)
   const char* force_generic = getenv("KRIPKE_SPLIT_GENERIC");

@@ -449,6 +449,130 @@ def frame_family(n: int, count: int, start: int = 0, seed: int = SEED_C4) -> np.
     return succ
 
 
+# ------------------------------------------------- adversarial frame generators
+SEED_ADV = 0x4B52495000000007
+ADVERSARIAL = ("erdos-renyi", "edge-flip", "scc-bottleneck", "dead-end", "back-edge",
+               "permuted-bottleneck")
+
+
+def adversarial_frames(generator: str, n: int, count: int, start: int = 0,
+                       seed: int = SEED_ADV) -> np.ndarray:
+    """Frames start .. start+count-1 of one adversarial generator on n worlds (the
+    generator families of Section 7's adversarial frame synthesis), as uint32[count][n]
+    successor masks, each frame from its own counter-based SplitMix64 stream:
+      erdos-renyi          each ordered pair (loops included) with probability
+                           (1 + k mod 8) / 20, stratified over k;
+      edge-flip            a canonical seed (k mod 4: path, cycle, reverse path, star from
+                           world 0) with 1 + k mod 3 uniformly chosen pairs flipped;
+      scc-bottleneck       worlds cut into 2 + k mod 3 consecutive blocks, each a cycle
+                           with one random chord, block i linked to block i+1 by one edge;
+      dead-end             a random out-tree plus random back edges, then 1 + k mod 3
+                           worlds emptied;
+      back-edge            the path 0 -> ... -> n-1 plus 1 + k mod 4 edges (i, j), j < i;
+      permuted-bottleneck  scc-bottleneck with the world labels permuted."""
+    assert 1 <= n <= 16 and generator in ADVERSARIAL
+    g = ADVERSARIAL.index(generator)
+    k = np.arange(start, start + count, dtype=np.int64)
+    base = mix64(seed ^ (n << 48) ^ (g << 40))
+    with np.errstate(over="ignore"):
+        st0 = np.uint64(base) + k.astype(np.uint64) * np.uint64((512 * GAMMA) & MASK64)
+
+    def draw(j: int) -> np.ndarray:
+        with np.errstate(over="ignore"):
+            return mix64_np(st0 + np.uint64(((j + 1) * GAMMA) & MASK64))
+
+    rows = np.arange(count)
+    succ = np.zeros((count, n), dtype=np.uint32)
+    one = np.uint32(1)
+
+    def add(mask, src, dst):
+        idx = np.nonzero(mask)[0]
+        np.bitwise_or.at(succ, (idx, src[idx]), (one << dst[idx].astype(np.uint32)))
+
+    def flip(mask, src, dst):
+        idx = np.nonzero(mask)[0]
+        np.bitwise_xor.at(succ, (idx, src[idx]), (one << dst[idx].astype(np.uint32)))
+
+    def bottleneck():
+        nb = 2 + (k % 3)
+        for b in range(2, 5):
+            m = nb == b
+            size = n // b
+            for blk in range(b):
+                lo = blk * size
+                hi = n if blk == b - 1 else lo + size
+                ln = hi - lo
+                for i in range(lo, hi):  # a cycle through the block
+                    add(m, np.full(count, i), np.full(count, lo + (i - lo + 1) % ln))
+                c1 = lo + below_np(draw(8 * blk), ln).astype(np.int64)
+                c2 = lo + below_np(draw(8 * blk + 1), ln).astype(np.int64)
+                add(m, c1, c2)
+                if blk + 1 < b:
+                    nlo = hi
+                    nhi = n if blk + 1 == b - 1 else nlo + size
+                    s_ = lo + below_np(draw(8 * blk + 2), ln).astype(np.int64)
+                    d_ = nlo + below_np(draw(8 * blk + 3), nhi - nlo).astype(np.int64)
+                    add(m, s_, d_)
+
+    if generator == "erdos-renyi":
+        thr = (1 + (k % 8)).astype(np.uint64)
+        for u in range(n):
+            for v in range(n):
+                hit = below_np(draw(u * n + v), 20) < thr
+                add(hit, np.full(count, u), np.full(count, v))
+    elif generator == "edge-flip":
+        kind = k % 4
+        for i in range(n - 1):
+            add(kind == 0, np.full(count, i), np.full(count, i + 1))
+            add(kind == 2, np.full(count, i + 1), np.full(count, i))
+        for i in range(n):
+            add(kind == 1, np.full(count, i), np.full(count, (i + 1) % n))
+            if i > 0:
+                add(kind == 3, np.full(count, 0), np.full(count, i))
+        nflip = 1 + (k % 3)
+        for t in range(3):
+            u = below_np(draw(2 * t), n).astype(np.int64)
+            v = below_np(draw(2 * t + 1), n).astype(np.int64)
+            flip(nflip > t, u, v)
+    elif generator in ("scc-bottleneck", "permuted-bottleneck"):
+        bottleneck()
+    elif generator == "dead-end":
+        for i in range(1, n):
+            parent = below_np(draw(i), i).astype(np.int64)
+            add(np.ones(count, bool), parent, np.full(count, i))
+        for t in range(3):
+            u = below_np(draw(100 + 2 * t), n).astype(np.int64)
+            v = below_np(draw(101 + 2 * t), n).astype(np.int64)
+            add(v <= u, u, v)
+        ndead = 1 + (k % 3)
+        for t in range(3):
+            w = below_np(draw(200 + t), n).astype(np.int64)
+            idx = np.nonzero(ndead > t)[0]
+            succ[idx, w[idx]] = 0
+    else:  # back-edge
+        for i in range(n - 1):
+            add(np.ones(count, bool), np.full(count, i), np.full(count, i + 1))
+        nback = 1 + (k % 4)
+        for t in range(4):
+            i = 1 + below_np(draw(2 * t), max(n - 1, 1)).astype(np.int64)
+            j = below_np(draw(2 * t + 1), n).astype(np.int64) % np.maximum(i, 1)
+            add((nback > t) & (i < n), np.minimum(i, n - 1), j)
+    if generator == "permuted-bottleneck":
+        perm = np.tile(np.arange(n, dtype=np.int64), (count, 1))
+        for i in range(n - 1, 0, -1):
+            j = below_np(draw(300 + i), i + 1).astype(np.int64)
+            a = perm[rows, i].copy()
+            perm[rows, i] = perm[rows, j]
+            perm[rows, j] = a
+        out = np.zeros_like(succ)
+        for u in range(n):
+            for v in range(n):
+                bit = (succ[:, u] >> np.uint32(v)) & one
+                np.bitwise_or.at(out, (rows, perm[:, u]), bit << perm[:, v].astype(np.uint32))
+        succ = out
+    return succ
+
+
 def path_frame(n: int) -> list[int]:
     """Directed path 0 -> 1 -> ... -> n-1 as successor masks."""
     return [(1 << (w + 1)) if w + 1 < n else 0 for w in range(n)]

@@ -104,3 +104,15 @@ def test_census_enumeration_count():
         t[s] = 3 * t[s - 1] + 3 * sum(t[a] * t[s - 1 - a] for a in range(1, s - 1))
     assert [sizes.count(s) for s in range(1, 8)] == [t[s] for s in range(1, 8)]
     assert len(I.all_pointed_models(3, 2)) == 64 + 512 + 98304
+
+
+def test_adversarial_generators_deterministic_and_in_range():
+    for g in I.ADVERSARIAL:
+        for n in (6, 11, 16):
+            a = I.adversarial_frames(g, n, 300)
+            b = I.adversarial_frames(g, n, 100, start=200)
+            assert a.shape == (300, n) and (a < (1 << n)).all()
+            assert (a[200:] == b).all()
+    # bottleneck frames have no dead ends; the dead-end generator always has one
+    assert (I.adversarial_frames("scc-bottleneck", 12, 200) != 0).all()
+    assert ((I.adversarial_frames("dead-end", 12, 200) == 0).any(axis=1)).all()
