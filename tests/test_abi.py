@@ -63,3 +63,26 @@ def test_validation_errors_without_gpu(kr):
     assert _census_status(kr, [I.TOP], cls=4) == -1
     assert _census_status(kr, [I.TOP], out=None) == -1
     assert b"opcode" in kr.lib().kripke_last_error() or True
+
+
+def test_split_and_validity_limits_without_gpu(kr):
+    """Size limits of the split search and the validity maps are checked on the host."""
+    c, o = I.pack([[I.TOP], [I.BOT]])
+    cp = c.ctypes.data_as(C.POINTER(C.c_uint8))
+    op = o.ctypes.data_as(C.POINTER(C.c_uint32))
+    out = C.c_void_p(16)
+    split = kr.lib().kripke_split_batch
+    assert split(cp, op, 1, out, 4, 17, 0, out, None) == -3      # more than 16 worlds
+    assert split(cp, op, 1, out, 4, 12, 3, out, None) == -3      # nvars * n > 24
+    assert split(cp, op, 1, out, 4, 8, 4, out, None) == -3       # four variables on 8 worlds
+    assert split(cp, op, 0, out, 4, 8, 0, out, None) == -1       # empty batch
+    assert split(cp, op, 1, None, 4, 8, 0, out, None) == -1      # frames missing
+    c1, o1 = I.pack([[I.TOP]])
+    cp1 = c1.ctypes.data_as(C.POINTER(C.c_uint8))
+    op1 = o1.ctypes.data_as(C.POINTER(C.c_uint32))
+    valid = kr.lib().kripke_frame_validity
+    assert valid(cp1, op1, 1, 3, 2, out, None) == -3             # n < 4
+    assert valid(cp1, op1, 1, 6, 2, out, None) == -3             # n > 5
+    assert valid(cp1, op1, 1, 4, 3, out, None) == -3             # n * nvars > 11
+    assert valid(cp1, op1, 1, 4, 2, None, None) == -1            # output missing
+    assert b"n" in kr.lib().kripke_last_error()
