@@ -404,14 +404,17 @@ __device__ __forceinline__ void run(Ctx<N, NV, LS, MODE>& c, const uint32_t* pro
 template <int N, int NV, int LS, int MODE>
 __device__ __forceinline__ uint64_t candidate(const Ctx<N, NV, LS, MODE>& c, int s, uint32_t fail,
                                               uint64_t bal, uint64_t blk, uint32_t chunk,
-                                              int lane) {
+                                              int lane, bool all_fail) {
   using G = Geo<N, NV, LS, MODE>;
   const int fl = __builtin_ctzll(bal);
   const uint32_t j = __builtin_ctz(fail | 0x80000000u);
+  // an all-fail program (BOT) fails first at world 0; its accumulator is not set
   uint32_t world = 0;
+  if (!all_fail) {
 #pragma unroll
-  for (int w = N - 1; w >= 0; --w)
-    if (!((c.acc[s][w] >> j) & 1u)) world = w;
+    for (int w = N - 1; w >= 0; --w)
+      if (!((c.acc[s][w] >> j) & 1u)) world = w;
+  }
   // list mode: the key's frame field is the list position, and the set is a
   // valuation field
   const uint64_t pos = G::LIST ? blk
@@ -543,29 +546,28 @@ void census_fast(FastArgs a) {
 #pragma unroll
         for (int i = 0; i < G::CHB; ++i)
           c.ch[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)(0u - ((chunk >> i) & 1u)));
-        if (all_fail) {
-#pragma unroll
-          for (int ss = 0; ss < G::S; ++ss)
-#pragma unroll
-            for (int w = 0; w < N; ++w) c.acc[ss][w] = 0u;
-        } else {
-          run<N, NV, LS, MODE>(c, prog, first, pw >> 1);
-        }
+        if (!all_fail) run<N, NV, LS, MODE>(c, prog, first, pw >> 1);
         const uint32_t lvl_word = FUSED ? __builtin_amdgcn_readfirstlane(
                                               lvl_raw >> ((uint32_t)(pbase & 15) * 2))
                                         : 0u;
         const bool classy = FUSED && (lvl_word & (G::B >= 4 ? 0xFFFFFFFFu
                                                   : ((1u << (2 << G::B)) - 1u))) != 0;
-#pragma unroll
-        for (int s = 0; s < G::S; ++s) {
+        // failing (valuation) bits of set s on this lane
+        auto fail_of = [&](int s) {
           uint32_t all = ~0u;
 #pragma unroll
           for (int w = 0; w < N; ++w) all &= c.acc[s][w];
-          uint32_t fail = ~all;
+          uint32_t fail = all_fail ? ~0u : ~all;
           if (ragged) {
             const uint64_t pos = pbase | ((uint64_t)s << G::LF) | lane_pos;
             if (pos < a.pos_begin || pos >= a.pos_end) fail = 0;
           }
+          return fail;
+        };
+        uint32_t anyfail = 0;
+#pragma unroll
+        for (int s = 0; s < G::S; ++s) {
+          const uint32_t fail = fail_of(s);
           cnt[0] += __builtin_popcount(fail);
           if constexpr (kMaps) {
             if (a.valid_bits) {
@@ -580,13 +582,7 @@ void census_fast(FastArgs a) {
               vbits |= (~inv & ((1u << (1 << G::LF)) - 1u)) << (s << G::LF);
             }
           }
-          if (key[0] == ~0ull) {
-            const uint64_t bal = __ballot(fail != 0);
-            if (bal) {
-              const uint64_t k = candidate(c, s, fail, bal, blk, chunk, lane);
-              best[0] = k < best[0] ? k : best[0];
-            }
-          }
+          anyfail |= fail;
           if constexpr (FUSED) {
             if (classy) {
               const uint32_t lvl = (lvl_word >> (2 * ((s << G::LF) | lane_pos))) & 3u;
@@ -597,10 +593,28 @@ void census_fast(FastArgs a) {
                 if (key[k] == ~0ull) {
                   const uint64_t bal = __ballot(fk != 0);
                   if (bal) {
-                    const uint64_t kk = candidate(c, s, fk, bal, blk, chunk, lane);
+                    const uint64_t kk = candidate(c, s, fk, bal, blk, chunk, lane, all_fail);
                     best[k] = kk < best[k] ? kk : best[k];
                   }
                 }
+              }
+            }
+          }
+        }
+        // one ballot per block while no key is known; then the least key lies in
+        // the first failing set (sets follow frame positions, or, in list mode,
+        // valuation bits above the lane bits)
+        if (key[0] == ~0ull && __ballot(anyfail != 0)) {
+          bool found = false;
+#pragma unroll
+          for (int s = 0; s < G::S; ++s) {
+            if (!found) {
+              const uint32_t fail = fail_of(s);
+              const uint64_t bal = __ballot(fail != 0);
+              if (bal) {
+                const uint64_t k = candidate(c, s, fail, bal, blk, chunk, lane, all_fail);
+                best[0] = k < best[0] ? k : best[0];
+                found = true;
               }
             }
           }
