@@ -254,6 +254,47 @@ def test_fused_plan_matches_single_class(kr, n, nvars, getter, count):
         kr.kripke_plan_destroy(plan)
 
 
+def test_bench_plan_full_batch_sampled(kr, orc):
+    """The measured configuration itself: the whole 4,096-formula n = 5 batch in one fused
+    plan with the committed tile choices (as the benchmark runs it).  Sampled formulas are
+    checked against the oracle in every class: first K keys on a key-order prefix, T keys
+    as reflexive countermodels, exact keys and counts over the whole S4 and S5 layers;
+    every sixteenth K key is a certificate;
+    and K/T counts equal the single-class kernels' for the whole batch."""
+    import os
+    import torch
+    fs = I.config3_formulas()
+    code, offs = I.pack(fs)
+    cache = os.path.join(os.path.dirname(kr.__file__), "tune_cache.json")
+    plan = kr.kripke_plan_create(code, offs, 5, 0xF, 2, tune_cache=cache)
+    out = torch.zeros((4, len(fs), 2), dtype=torch.int64, device="cuda")
+    try:
+        kr.kripke_plan_launch(plan, out)
+        torch.cuda.synchronize()
+        r = kr.as_u64(out)
+    finally:
+        kr.kripke_plan_destroy(plan)
+    rng = I.SplitMix64(0xBE4C, 0)
+    idx = sorted(set(rng.below(len(fs)) for _ in range(40)))
+    sub = [fs[i] for i in idx]
+    _check_first_keys(orc, sub, r[0, idx, 0], 5, 0, 2, 1 << 14)
+    for code, k in zip(sub, r[1, idx, 0]):  # T keys are reflexive countermodels
+        if int(k) != NONE:
+            f, val, w = orc.decode_key(int(k), 5, 2)
+            assert orc.check_certificate(code, I.frame_succ(f, 5), 2, val, w, 1)
+    for c in (2, 3):
+        ek, ec = _oracle_all(orc, sub, 5, c, 2, threads=0)
+        assert (r[c, idx, 0] == ek).all() and (r[c, idx, 1] == ec).all(), c
+    for c in (0, 1):
+        k, n = kr.census(fs, 5, c, 2)
+        assert (r[c, :, 0] == k).all() and (r[c, :, 1] == n).all(), c
+    for i, code in enumerate(fs):
+        k = int(r[0, i, 0])
+        if k != NONE and i % 16 == 0:
+            f, val, w = orc.decode_key(k, 5, 2)
+            assert orc.check_certificate(code, I.frame_succ(f, 5), 2, val, w, 0)
+
+
 def test_fused_plan_small_classes_vs_oracle(kr, orc):
     """Fused-plan S4 and S5 rows at n = 5 against the oracle directly."""
     import torch
