@@ -140,7 +140,8 @@ def bench_learned():
 def bench_reproduction():
     """The five-world census of Section 6 (paper: 1.63e14 evaluations in 45 minutes)."""
     from paper_2606_15437_amd import census_corpus as C
-    out, _, _ = C.run(log=log)
+    out, _, _ = C.run(log=log, tune_cache=os.path.join(ROOT, "paper_2606_15437_amd",
+                                                       "tune_cache.json"))
     out["G_evals_per_s_five_world"] = out["k_frame_evals"] / out["census_seconds"] / 1e9
     out["paper"] = {"raw_trees": 44678, "classes": 5621, "formulas": 5624,
                     "K_refuted_on_1": 5086, "K_refuted_on_2": 536, "K_survivors": 2,

@@ -62,9 +62,10 @@ def build_corpus(log=None):
     return raw, reps, corpus
 
 
-def census(formulas, log=None):
+def census(formulas, log=None, tune_cache=None):
     """Per formula and class: fail counts and least keys at n = 1..5, minimal
-    countermodel size (0: none through five worlds), timings and evaluation count."""
+    countermodel size (0: none through five worlds), timings and evaluation count.
+    tune_cache: autotuner cache for the five-world plan (None: default tiles)."""
     import torch
     code, offs = I.pack(formulas)
     B = len(formulas)
@@ -80,7 +81,7 @@ def census(formulas, log=None):
             keys[c, n - 1], counts[c, n - 1] = r[:, 0], r[:, 1]
     torch.cuda.synchronize()
     t_small = time.time() - t0
-    plan = K.kripke_plan_create(code, offs, 5, 0xF, 2)
+    plan = K.kripke_plan_create(code, offs, 5, 0xF, 2, tune_cache=tune_cache)
     out = torch.empty((4, B, 2), dtype=torch.int64, device="cuda")
     torch.cuda.synchronize()
     t1 = time.time()
@@ -119,9 +120,9 @@ def summary(res):
             "max_refuted_minimal_size": {c: int(m[i].max()) for i, c in enumerate(CLASSES)}}
 
 
-def run(log=print):
+def run(log=print, tune_cache=None):
     raw, reps, corpus = build_corpus(log)
-    res = census(corpus, log)
+    res = census(corpus, log, tune_cache)
     out = summary(res)
     out.update({"raw_trees": len(raw), "classes": int(len(reps)), "formulas": len(corpus),
                 "census_seconds": res["seconds"], "five_world_seconds": res["five_world_seconds"],
