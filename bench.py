@@ -308,7 +308,13 @@ def main():
             _, _, threads = orc.census(f, n, 0, nvars, 0, F, threads=0)
         dt = time.time() - t0
         cpu_evals = float(len(sub)) * F * nval
+        # the same oracle on one thread, over a sixty-fourth of the frames
+        t1 = time.time()
+        for f in sub:
+            orc.census(f, n, 0, nvars, 0, F // 64, threads=1)
+        single = float(len(sub)) * (F // 64) * nval / (time.time() - t1) / 1e9
         cpu = {"value": cpu_evals / dt / 1e9, "unit": "G evals/s", "cores": threads,
+               "single_thread_value": single,
                "kind": "oracle",
                "sample": f"first {len(sub)} formulas of the 4,096-formula batch x frames "
                          f"[0, 2^{args.cpu_frames_log2}) x {nval} valuations, class K "
