@@ -19,7 +19,7 @@ Also reported in the JSON line:
   - split: the split search (Definition 2, Proposition 5) of formula pairs that agree on
     every model with at most 4 worlds, over the 6-, 7- and 8-world frame families;
   - learned: the learned pair proposal at full scale (10,000-formula corpus, ~5.5M-pair
-    universe, 10^6 budget), every proposal judged exactly, against plain enumeration;
+    universe, 10^6 budget), every proposal verified exactly, against plain enumeration;
   - census_reproduction: the paper's five-world census (Section 6): 44,678 enumerated
     formulas -> 5,621 classes -> 5,624 formulas x K/T/S4/S5 x every frame n <= 5;
   - active_synthesis: the 32 context-iteration pairs of Section 7, exact through five

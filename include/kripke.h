@@ -230,7 +230,8 @@ int kripke_select_top(const float *d_scores, uint64_t n, uint64_t budget, uint64
                       void *stream);
 
 /*
- * Pair-scoring MLP (spec learned proposal): input
+ * Pair-scoring MLP (the learned proposal; it stands in for the representation
+ * layouts of Section 9's retrieval): input
  * [sig_a XOR sig_b, sig_a AND sig_b] of two 4,096-bit signatures (8,192
  * values in {0,1}) -> 512 -> 256 -> 1, ReLU; BF16 weights and activations as
  * matrix-core operands, FP32 accumulation, FP32 master weights, Adam.

@@ -1,4 +1,4 @@
-"""Learned pair proposal: rank candidate formula pairs by a trained MLP, then judge every
+"""Learned pair proposal: rank candidate formula pairs by a trained MLP, then verify every
 proposal exactly with the census and split kernels.
 
 A *late split* (the retrieval target) is a pair (phi, psi) whose biconditional
@@ -92,7 +92,7 @@ def _pairs_host(d_pairs):
 
 
 class Verifier:
-    """Exact judge of pairs: agreement through 4 worlds, then a split on the panel."""
+    """Exact verdicts on pairs: agreement through 4 worlds, then a split on the panel."""
 
     def __init__(self, formulas, panel=None, chunk=1 << 17, log=None):
         torch = _t()
@@ -170,7 +170,7 @@ class Verifier:
                 self.log(f"  split n={n}: {len(idx)} in, {int((where == n).sum())} split")
         return found, where
 
-    def judge(self, d_pairs_or_host):
+    def verify(self, d_pairs_or_host):
         """Per pair: 1 if it is a late split (agrees through 4 worlds, splits on the panel)."""
         ia, ib = _pairs_host(d_pairs_or_host)
         hit = np.zeros(len(ia), dtype=bool)
@@ -233,7 +233,7 @@ def hamming_scores(d_sig, d_pairs):
 def run(n_test=10000, n_train=10000, universe_pairs=5_500_000, train_pairs=5_500_000,
         budget=1_000_000, steps=2000, panel_frames=4096, log=print, details=False):
     """The full protocol; returns a dict of hit counts and timings.  With details, also
-    the judged pairs (host arrays) under "details": canonical pair codes of the verified
+    the verified pairs (host arrays) under "details": canonical pair codes of the verified
     union, hit flags, agreement flags, separating keys and the n they were found at."""
     torch = _t()
     t0 = time.time()
@@ -246,7 +246,7 @@ def run(n_test=10000, n_train=10000, universe_pairs=5_500_000, train_pairs=5_500
     k_train, u_tr = universe_of_size(s_tr, train_pairs)
     log(f"training universe {u_tr.shape[0]} pairs ({time.time() - t0:.1f} s)")
     ver_tr = Verifier(train, panel, log=log)
-    lab, _ = ver_tr.judge(u_tr)
+    lab, _ = ver_tr.verify(u_tr)
     rec["train"] = {"formulas": n_train, "k": k_train, "pairs": int(u_tr.shape[0]),
                     "positives": int(lab.sum()),
                     "label_evals": ver_tr.evals, "label_s": time.time() - t0}
@@ -270,10 +270,10 @@ def run(n_test=10000, n_train=10000, universe_pairs=5_500_000, train_pairs=5_500
     rankings["learned"] = top(z, budget)
     rankings["plain"] = torch.arange(min(budget, npairs), device="cuda")
     rankings["hamming"] = top(hamming_scores(s_te, u_te), budget)
-    # judge the union once, then count per ranking
+    # verify the union once, then count per ranking
     union = torch.unique(torch.cat([r for r in rankings.values()]))
     t3 = time.time()
-    hit_u, info = ver.judge(u_te[union])
+    hit_u, info = ver.verify(u_te[union])
     rec["test"]["verify_s"] = time.time() - t3
     rec["test"]["verify_evals"] = ver.evals
     union_h = union.cpu().numpy()  # sorted
