@@ -94,6 +94,17 @@ struct Geo {
   // residency at three blocks per CU (programs needing two slots run in the
   // LS = 2 tier instead)
   static constexpr int LDS_SLOTS = LS >= 3 ? 0 : 1;
+  // Block-uniform relation words held in vector registers: on gfx950 a VALU
+  // instruction with a scalar operand issues at half the rate of one with
+  // vector operands only, and the modal terms are most of the work.  List
+  // mode (up to 64 uniform words) keeps them scalar.
+  static constexpr bool RUV = !LIST;
+  // sets of each register stack slot that live in registers; the others sit
+  // in the wave's LDS area (at eight sets this keeps the kernel within 128
+  // VGPRs, four waves per SIMD, with the relation words in registers)
+  static constexpr int SR = (RUV && LS >= 3) ? S - 2 : S;
+  // LDS words per lane: the LDS slots, then the register slots' LDS sets
+  static constexpr int LDS_WORDS = (LDS_SLOTS * S + DS * (S - SR)) * N;
 };
 
 // Diagonal positions whose relation bit is shared by the whole block (mode K):
@@ -111,14 +122,16 @@ __host__ __device__ constexpr uint64_t diag_uniform_mask() {
 template <int N, int NV, int LS, int MODE>
 struct Ctx {
   using G = Geo<N, NV, LS, MODE>;
-  uint32_t ru[N][N];                    // uniform relation words of the block
+  uint32_t ru[N][N];                    // uniform relation words of the block (VGPRs if RUV)
   uint32_t pv[5];                       // in-word valuation patterns, kept in VGPRs
   uint32_t lm[G::LF > 0 ? G::LF : 1];   // per-lane frame-bit words
   uint32_t lv[G::LV > 0 ? G::LV : 1];   // per-lane valuation-bit words
   uint32_t ch[G::CHB > 0 ? G::CHB : 1]; // uniform valuation-chunk words
   uint32_t acc[G::S][N];
   uint32_t stk[G::DS][G::S][N];
-  uint32_t* spill;  // this wave's LDS overflow slots: [LDS_SLOTS][S][N][64 lanes]
+  // this wave's LDS stack area, lane-minor: [LDS_SLOTS][S][N][64], then
+  // [DS][S - SR][N][64] for the sets of the register slots held in LDS
+  uint32_t* spill;
   int lane;
 };
 
@@ -186,6 +199,12 @@ __device__ __forceinline__ uint32_t bin_lit(uint32_t a, uint32_t x) {
   return __builtin_amdgcn_bitop3_b32(a, x, x, tt);
 }
 
+// a == b bitwise as v_bitop3 (v_xnor_b32 issues at half rate on gfx950)
+__device__ __forceinline__ uint32_t xnor3(uint32_t a, uint32_t b) {
+  constexpr unsigned tt = truth_table([](int a, int b, int) { return a == b; });
+  return __builtin_amdgcn_bitop3_b32(a, b, b, tt);
+}
+
 __device__ __forceinline__ uint32_t opaque_not(uint32_t x) {
   uint32_t r;
   asm volatile("v_not_b32 %0, %1" : "=v"(r) : "v"(x));
@@ -212,7 +231,7 @@ __device__ __forceinline__ void f_bin_leaf(Ctx<N, NV, LS, MODE>& c) {
     KR_FOR_SW {
       const uint32_t y = leaf<N, NV, LS, MODE, L>(c, s, w);
       c.acc[s][w] = OP == 0 ? (c.acc[s][w] & y) : OP == 1 ? (c.acc[s][w] | y)
-                                                          : ~(c.acc[s][w] ^ y);
+                                                          : xnor3(c.acc[s][w], y);
     }
   }
 }
@@ -222,15 +241,30 @@ template <int N, int NV, int LS, int MODE, int L>
 __device__ __forceinline__ void f_or(Ctx<N, NV, LS, MODE>& c) { f_bin_leaf<1, N, NV, LS, MODE, L>(c); }
 template <int N, int NV, int LS, int MODE, int L>
 __device__ __forceinline__ void f_iff(Ctx<N, NV, LS, MODE>& c) { f_bin_leaf<2, N, NV, LS, MODE, L>(c); }
-// Stack slots below DS live in registers; the next LDS_SLOTS spill to the
-// wave's LDS area (rare: only programs needing the extra slot touch it).
+// Stack slots below DS live in registers (sets below SR; the others in the
+// wave's LDS area); the next LDS_SLOTS live wholly in LDS (rare: only programs
+// needing the extra slot touch it).
+template <int N, int NV, int LS, int MODE>
+__device__ __forceinline__ int lds_word(int d, int s, int w) {
+  using G = Geo<N, NV, LS, MODE>;
+  if (d >= G::DS) return ((d - G::DS) * G::S + s) * N + w;
+  return G::LDS_SLOTS * G::S * N + (d * (G::S - G::SR) + (s - G::SR)) * N + w;
+}
+template <int N, int NV, int LS, int MODE>
+__device__ __forceinline__ bool in_regs(int d, int s) {
+  using G = Geo<N, NV, LS, MODE>;
+  return d < G::DS && s < G::SR;
+}
 template <int N, int NV, int LS, int MODE, int D>
 __device__ __forceinline__ void f_save(Ctx<N, NV, LS, MODE>& c) {
   using G = Geo<N, NV, LS, MODE>;
-  if constexpr (D < G::DS) {
-    KR_FOR_SW c.stk[D][s][w] = c.acc[s][w];
-  } else if constexpr (D < G::DS + G::LDS_SLOTS) {
-    KR_FOR_SW c.spill[(((D - G::DS) * G::S + s) * N + w) * 64 + c.lane] = c.acc[s][w];
+  if constexpr (D < G::DS + G::LDS_SLOTS) {
+    KR_FOR_SW {
+      if (in_regs<N, NV, LS, MODE>(D, s))
+        c.stk[D < G::DS ? D : 0][s][w] = c.acc[s][w];
+      else
+        c.spill[lds_word<N, NV, LS, MODE>(D, s, w) * 64 + c.lane] = c.acc[s][w];
+    }
   }
 }
 template <int N, int NV, int LS, int MODE, int D, int OP>
@@ -238,11 +272,12 @@ __device__ __forceinline__ void f_comb(Ctx<N, NV, LS, MODE>& c) {
   using G = Geo<N, NV, LS, MODE>;
   if constexpr (D < G::DS + G::LDS_SLOTS) {
     KR_FOR_SW {
-      const uint32_t y = D < G::DS ? c.stk[D < G::DS ? D : 0][s][w]
-                                   : c.spill[(((D - G::DS) * G::S + s) * N + w) * 64 + c.lane];
+      const uint32_t y = in_regs<N, NV, LS, MODE>(D, s)
+                             ? c.stk[D < G::DS ? D : 0][s][w]
+                             : c.spill[lds_word<N, NV, LS, MODE>(D, s, w) * 64 + c.lane];
       if constexpr (OP == 0) c.acc[s][w] &= y;
       else if constexpr (OP == 1) c.acc[s][w] |= y;
-      else c.acc[s][w] = ~(c.acc[s][w] ^ y);
+      else c.acc[s][w] = xnor3(c.acc[s][w], y);
     }
   }
 }
@@ -428,7 +463,7 @@ __device__ __forceinline__ uint64_t candidate(const Ctx<N, NV, LS, MODE>& c, int
 }
 
 template <int N, int NV, int LS, int MODE, bool FUSED>
-// The eight-set variants are held to 128 VGPRs: four waves per SIMD.
+// The eight-set variants run three waves per SIMD (at most 168 VGPRs).
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LS >= 3 ? 4 : 1)))
 void census_fast(FastArgs a) {
   using G = Geo<N, NV, LS, MODE>;
@@ -436,7 +471,11 @@ void census_fast(FastArgs a) {
   static_assert(!G::LIST || (G::V >= 11 + LS && !FUSED),
                 "list mode needs the lane and set bits to be valuation bits");
   __shared__ uint32_t sprog[4][kMaxMicro / 4 + 4];
-  __shared__ uint32_t sspill[4][G::LDS_SLOTS > 0 ? G::LDS_SLOTS * G::S * N * 64 : 1];
+  __shared__ uint32_t sspill[4][G::LDS_WORDS > 0 ? G::LDS_WORDS * 64 : 1];
+  // fused mode: per-lane failure counts of the classes T, S4, S5, private to
+  // the lane (only blocks that can hold a reflexive frame touch them, so they
+  // need not occupy registers through the interpreter)
+  __shared__ uint32_t scls[4][FUSED ? 3 : 1][64];
   const int lane = threadIdx.x & 63;
   uint32_t* prog = sprog[threadIdx.x >> 6];
   constexpr int NC = FUSED ? 4 : 1;
@@ -495,9 +534,12 @@ void census_fast(FastArgs a) {
     if (first == (uint64_t)(U_LOAD + L_TOP)) continue;
     const bool all_fail = first == (uint64_t)(U_LOAD + L_BOT);
 
-    uint32_t cnt[NC];
+    uint32_t cnt0 = 0;
+    uint32_t* ccls = &scls[threadIdx.x >> 6][0][lane];  // class k at ccls[(k - 1) * 64]
+    if constexpr (FUSED) {
 #pragma unroll
-    for (int k = 0; k < NC; ++k) cnt[k] = 0;
+      for (int k = 1; k < NC; ++k) ccls[(k - 1) * 64] = 0;
+    }
     uint64_t key[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) key[k] = ~0ull;
@@ -516,16 +558,29 @@ void census_fast(FastArgs a) {
       } else {
         base = MODE == 0 ? pbase : refl_frame(pbase, N);
       }
+      // the relation bits in vector registers, expanded there by one signed
+      // bit-field extract per word (opaque, so the words stay vector values)
+      uint32_t vbase[2] = {0u, 0u};
+      if constexpr (G::RUV) {
+        asm volatile("v_mov_b32 %0, %1" : "=v"(vbase[0]) : "s"((uint32_t)base));
+        if constexpr (N * N > 32)
+          asm volatile("v_mov_b32 %0, %1" : "=v"(vbase[1]) : "s"((uint32_t)(base >> 32)));
+      }
 #pragma unroll
       for (int w = 0; w < N; ++w)
 #pragma unroll
         for (int v = 0; v < N; ++v) {
           const int p = w * N + v;
           if (role<N, MODE, G::LF, LS>(p) != R_UNIFORM) continue;
-          if (N * N <= 32)  // one scalar signed bit-field extract per word
+          if constexpr (G::RUV) {
+            uint32_t r;
+            asm volatile("v_bfe_i32 %0, %1, %2, 1" : "=v"(r) : "v"(vbase[p >> 5]), "i"(p & 31));
+            c.ru[w][v] = r;
+          } else if (N * N <= 32) {  // one scalar signed bit-field extract per word
             c.ru[w][v] = (uint32_t)__builtin_amdgcn_sbfe((int)(uint32_t)base, p, 1);
-          else
+          } else {
             c.ru[w][v] = 0u - (uint32_t)((base >> p) & 1u);
+          }
         }
       // valid (lane, set) pairs: positions inside [pos_begin, pos_end)
       const bool ragged = !G::LIST && (blk == rag_lo || blk == rag_hi);
@@ -568,7 +623,7 @@ void census_fast(FastArgs a) {
 #pragma unroll
         for (int s = 0; s < G::S; ++s) {
           const uint32_t fail = fail_of(s);
-          cnt[0] += __builtin_popcount(fail);
+          cnt0 += __builtin_popcount(fail);
           if constexpr (kMaps) {
             if (a.valid_bits) {
               // a frame's valuations fill 2^LV consecutive lanes: it is valid
@@ -589,7 +644,7 @@ void census_fast(FastArgs a) {
 #pragma unroll
               for (int k = 1; k < NC; ++k) {
                 const uint32_t fk = lvl >= (uint32_t)k ? fail : 0u;
-                cnt[k] += __builtin_popcount(fk);
+                ccls[(k - 1) * 64] += __builtin_popcount(fk);
                 if (key[k] == ~0ull) {
                   const uint64_t bal = __ballot(fk != 0);
                   if (bal) {
@@ -636,7 +691,7 @@ void census_fast(FastArgs a) {
     }
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      uint32_t ck = cnt[k];
+      uint32_t ck = k == 0 ? cnt0 : ccls[(k > 0 ? k - 1 : 0) * 64];
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) ck += __shfl_xor(ck, o);
       if (lane == 0) {
