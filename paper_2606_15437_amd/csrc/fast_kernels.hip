@@ -77,6 +77,18 @@ __host__ __device__ constexpr int role_idx(int p, int LF) {
   return r < LF ? r : r - LF;
 }
 
+// List-mode relation rows held in vector registers, per variant: as many as
+// fit four waves per SIMD (at most 128 VGPRs).  At n = 8 with four sets the
+// kernel also keeps two sets of its register stack slot in LDS and has no
+// whole LDS slot, which buys two more rows (measured on the split search:
+// 483 ms with three rows and an LDS slot, 459 ms with five).
+__host__ __device__ constexpr int list_rows(int n, int ls) {
+  return n == 6 ? 6 : n == 7 ? (ls == 0 ? 7 : ls == 1 ? 6 : 1) : (ls == 0 ? 6 : ls == 1 ? 5 : 5);
+}
+__host__ __device__ constexpr bool list_n8_four_sets(bool list, int n, int ls) {
+  return list && n >= 8 && ls == 2;
+}
+
 template <int N, int NV, int LS, int MODE>
 struct Geo {
   static constexpr bool LIST = MODE == 2;
@@ -87,22 +99,26 @@ struct Geo {
   static constexpr int SV = LIST ? LS : 0;                       // set bits that are valuation bits
   static constexpr int B = LIST ? 0 : LF + LS;                   // log2 frames per block
   static constexpr int CHB = V > 11 + SV ? V - 11 - SV : 0;      // valuation chunk bits
-  // stack slots in registers (one at the 8-world LIST variant with four
-  // sets, which keeps it at 105 VGPRs: four waves per SIMD)
-  static constexpr int DS = LS == 0 ? 4 : (LS <= 2 && !(LIST && N >= 8 && LS == 2)) ? 2 : 1;
-  // + slots spilled to LDS; none at LS = 3, whose 40 KB per block would cap
-  // residency at three blocks per CU (programs needing two slots run in the
-  // LS = 2 tier instead)
-  static constexpr int LDS_SLOTS = LS >= 3 ? 0 : 1;
-  // Block-uniform relation words held in vector registers: on gfx950 a VALU
-  // instruction with a scalar operand issues at half the rate of one with
-  // vector operands only, and the modal terms are most of the work.  List
-  // mode (up to 64 uniform words) keeps them scalar.
-  static constexpr bool RUV = !LIST;
+  // stack slots in registers (one at the eight-world four-set list variant)
+  static constexpr int DS = LS == 0 ? 4 : (LS <= 2 && !list_n8_four_sets(LIST, N, LS)) ? 2 : 1;
+  // + slots held wholly in LDS; none at LS = 3 (40 KB per block would cap
+  // residency at three blocks per CU) nor in the eight-world four-set list
+  // variant (its LDS stack sets already take 16 KB per block): programs
+  // needing more slots run in a narrower tier
+  static constexpr int LDS_SLOTS = LS >= 3 || list_n8_four_sets(LIST, N, LS) ? 0 : 1;
+  // Block-uniform relation words held in vector registers, by rows of the
+  // relation: on gfx950 a VALU instruction with a scalar operand issues at
+  // half the rate of one with vector operands only, and the modal terms are
+  // most of the work.  Census modes hold every row; list mode (n^2 uniform
+  // words) holds the rows that fit its register budget, the rest stay scalar.
+  static constexpr int RV_ROWS = !LIST ? N : list_rows(N, LS);
+  static constexpr bool RUV = RV_ROWS > 0;
+  static constexpr int WPE = LS >= 3 || LIST ? 4 : 1;
   // sets of each register stack slot that live in registers; the others sit
-  // in the wave's LDS area (at eight sets this keeps the kernel within 128
-  // VGPRs, four waves per SIMD, with the relation words in registers)
-  static constexpr int SR = (RUV && LS >= 3) ? S - 2 : S;
+  // in the wave's LDS area (this keeps the eight-set census variant and the
+  // eight-world four-set list variant within 128 VGPRs with their relation
+  // rows in registers)
+  static constexpr int SR = (RUV && LS >= 3) || list_n8_four_sets(LIST, N, LS) ? S - 2 : S;
   // LDS words per lane: the LDS slots, then the register slots' LDS sets
   static constexpr int LDS_WORDS = (LDS_SLOTS * S + DS * (S - SR)) * N;
 };
@@ -463,8 +479,9 @@ __device__ __forceinline__ uint64_t candidate(const Ctx<N, NV, LS, MODE>& c, int
 }
 
 template <int N, int NV, int LS, int MODE, bool FUSED>
-// The eight-set variants run three waves per SIMD (at most 168 VGPRs).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LS >= 3 ? 4 : 1)))
+// The eight-set and list variants are sized for four waves per SIMD.
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(Geo<N, NV, LS, MODE>::WPE)))
 void census_fast(FastArgs a) {
   using G = Geo<N, NV, LS, MODE>;
   static_assert(G::V >= 5, "fast kernel needs n * nvars >= 5");
@@ -563,7 +580,7 @@ void census_fast(FastArgs a) {
       uint32_t vbase[2] = {0u, 0u};
       if constexpr (G::RUV) {
         asm volatile("v_mov_b32 %0, %1" : "=v"(vbase[0]) : "s"((uint32_t)base));
-        if constexpr (N * N > 32)
+        if constexpr (N * G::RV_ROWS > 32)
           asm volatile("v_mov_b32 %0, %1" : "=v"(vbase[1]) : "s"((uint32_t)(base >> 32)));
       }
 #pragma unroll
@@ -572,7 +589,7 @@ void census_fast(FastArgs a) {
         for (int v = 0; v < N; ++v) {
           const int p = w * N + v;
           if (role<N, MODE, G::LF, LS>(p) != R_UNIFORM) continue;
-          if constexpr (G::RUV) {
+          if (w < G::RV_ROWS) {
             uint32_t r;
             asm volatile("v_bfe_i32 %0, %1, %2, 1" : "=v"(r) : "v"(vbase[p >> 5]), "i"(p & 31));
             c.ru[w][v] = r;
