@@ -347,6 +347,35 @@ __device__ __forceinline__ void f_modal(Ctx<N, NV, LS, MODE>& c) {
   }
 }
 
+// Two modal operators in a row (one micro-op): the first writes temporaries,
+// the second reads them and writes the accumulator directly, since the
+// accumulator's old words are dead by then, so no retiring moves are needed.
+template <bool DIA1, bool DIA2, int N, int NV, int LS, int MODE>
+__device__ __forceinline__ void f_modal2(Ctx<N, NV, LS, MODE>& c) {
+#pragma unroll
+  for (int s = 0; s < Geo<N, NV, LS, MODE>::S; ++s) {
+    uint32_t t[N];
+#pragma unroll
+    for (int w = 0; w < N; ++w) asm volatile("" : "+v"(c.acc[s][w]));
+#pragma unroll
+    for (int w = 0; w < N; ++w) {
+      uint32_t r = DIA1 ? 0u : ~0u;
+#pragma unroll
+      for (int v = 0; v < N; ++v) r = modal_term<DIA1>(c, s, w, v, c.acc[s][v], r);
+      t[w] = r;
+    }
+#pragma unroll
+    for (int w = 0; w < N; ++w) asm volatile("" : "+v"(t[w]));
+#pragma unroll
+    for (int w = 0; w < N; ++w) {
+      uint32_t r = DIA2 ? 0u : ~0u;
+#pragma unroll
+      for (int v = 0; v < N; ++v) r = modal_term<DIA2>(c, s, w, v, t[v], r);
+      c.acc[s][w] = r;
+    }
+  }
+}
+
 // DIA/BOX applied directly to a literal: the literal's words are read in
 // place instead of being loaded into the accumulator first.
 template <bool DIA, int N, int NV, int LS, int MODE, int L>
@@ -430,10 +459,10 @@ __device__ __forceinline__ void run(Ctx<N, NV, LS, MODE>& c, const uint32_t* pro
       KR_D8(U_IFF_S, G_IFFS)
       KR_L8(U_DIA_L, G_DIAL)
       KR_L8(U_BOX_L, G_BOXL)
-      case U_MM + 0: f_modal<false, N, NV, LS, MODE>(c); f_modal<false, N, NV, LS, MODE>(c); break;
-      case U_MM + 1: f_modal<false, N, NV, LS, MODE>(c); f_modal<true, N, NV, LS, MODE>(c); break;
-      case U_MM + 2: f_modal<true, N, NV, LS, MODE>(c); f_modal<false, N, NV, LS, MODE>(c); break;
-      case U_MM + 3: f_modal<true, N, NV, LS, MODE>(c); f_modal<true, N, NV, LS, MODE>(c); break;
+      case U_MM + 0: f_modal2<false, false, N, NV, LS, MODE>(c); break;
+      case U_MM + 1: f_modal2<false, true, N, NV, LS, MODE>(c); break;
+      case U_MM + 2: f_modal2<true, false, N, NV, LS, MODE>(c); break;
+      case U_MM + 3: f_modal2<true, true, N, NV, LS, MODE>(c); break;
       default: __builtin_unreachable();
     }
 #undef G_LOAD
