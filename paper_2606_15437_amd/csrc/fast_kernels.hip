@@ -465,6 +465,13 @@ __device__ __forceinline__ void run(Ctx<N, NV, LS, MODE>& c, const uint32_t* pro
       case U_MM + 3: f_modal2<true, true, N, NV, LS, MODE>(c); break;
       default: __builtin_unreachable();
     }
+    // Pinning the accumulator at the end of every handler lets the register
+    // allocator give it one home across the loop; without this it carries a
+    // few words in a second set of registers, copied back on every micro-op.
+#pragma unroll
+    for (int s = 0; s < Geo<N, NV, LS, MODE>::S; ++s)
+#pragma unroll
+      for (int w = 0; w < N; ++w) asm volatile("" : "+v"(c.acc[s][w]));
 #undef G_LOAD
 #undef G_AND
 #undef G_OR
