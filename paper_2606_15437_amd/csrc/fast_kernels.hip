@@ -434,16 +434,28 @@ __device__ __forceinline__ void run(Ctx<N, NV, LS, MODE>& c, const uint32_t* pro
     }
     const uint32_t op = (uint32_t)cur & 0xffu;
     cur >>= 8;
-#define G_LOAD(L) f_load<N, NV, LS, MODE, L>(c)
-#define G_AND(L) f_and<N, NV, LS, MODE, L>(c)
-#define G_OR(L) f_or<N, NV, LS, MODE, L>(c)
-#define G_IFF(L) f_iff<N, NV, LS, MODE, L>(c)
-#define G_SAVE(D) f_save<N, NV, LS, MODE, D>(c)
-#define G_ANDS(D) f_comb<N, NV, LS, MODE, D, 0>(c)
-#define G_ORS(D) f_comb<N, NV, LS, MODE, D, 1>(c)
-#define G_IFFS(D) f_comb<N, NV, LS, MODE, D, 2>(c)
-#define G_DIAL(L) f_modal_leaf<true, N, NV, LS, MODE, L>(c)
-#define G_BOXL(L) f_modal_leaf<false, N, NV, LS, MODE, L>(c)
+// Opcodes a program run by this variant cannot hold are unreachable: the
+// host compiler rejects variables beyond nvars (= NV), and every launch
+// path gives a variant only programs whose stack need fits its slots.
+// Dropping those cases shortens the dispatch tree and the code.
+#define KR_LEAF_OK(L) ((L) >= 8 || ((L) & 3) < NV)
+#define KR_SLOT_OK(D) ((D) < Geo<N, NV, LS, MODE>::DS + Geo<N, NV, LS, MODE>::LDS_SLOTS)
+#define KR_IF(OK, CALL) \
+  if constexpr (OK) {   \
+    CALL;               \
+  } else {              \
+    __builtin_unreachable(); \
+  }
+#define G_LOAD(L) KR_IF(KR_LEAF_OK(L), (f_load<N, NV, LS, MODE, L>(c)))
+#define G_AND(L) KR_IF(KR_LEAF_OK(L), (f_and<N, NV, LS, MODE, L>(c)))
+#define G_OR(L) KR_IF(KR_LEAF_OK(L), (f_or<N, NV, LS, MODE, L>(c)))
+#define G_IFF(L) KR_IF(KR_LEAF_OK(L), (f_iff<N, NV, LS, MODE, L>(c)))
+#define G_SAVE(D) KR_IF(KR_SLOT_OK(D), (f_save<N, NV, LS, MODE, D>(c)))
+#define G_ANDS(D) KR_IF(KR_SLOT_OK(D), (f_comb<N, NV, LS, MODE, D, 0>(c)))
+#define G_ORS(D) KR_IF(KR_SLOT_OK(D), (f_comb<N, NV, LS, MODE, D, 1>(c)))
+#define G_IFFS(D) KR_IF(KR_SLOT_OK(D), (f_comb<N, NV, LS, MODE, D, 2>(c)))
+#define G_DIAL(L) KR_IF(KR_LEAF_OK(L), (f_modal_leaf<true, N, NV, LS, MODE, L>(c)))
+#define G_BOXL(L) KR_IF(KR_LEAF_OK(L), (f_modal_leaf<false, N, NV, LS, MODE, L>(c)))
     switch (op) {
       KR_L10(U_LOAD, G_LOAD)
       case U_LOAD + L_TOP: G_LOAD(L_TOP); break;
@@ -472,6 +484,9 @@ __device__ __forceinline__ void run(Ctx<N, NV, LS, MODE>& c, const uint32_t* pro
     for (int s = 0; s < Geo<N, NV, LS, MODE>::S; ++s)
 #pragma unroll
       for (int w = 0; w < N; ++w) asm volatile("" : "+v"(c.acc[s][w]));
+#undef KR_IF
+#undef KR_LEAF_OK
+#undef KR_SLOT_OK
 #undef G_LOAD
 #undef G_AND
 #undef G_OR
