@@ -506,17 +506,16 @@ __device__ __forceinline__ void run(Ctx<N, NV, LS, MODE>& c, const uint32_t* pro
 template <int N, int NV, int LS, int MODE>
 __device__ __forceinline__ uint64_t candidate(const Ctx<N, NV, LS, MODE>& c, int s, uint32_t fail,
                                               uint64_t bal, uint64_t blk, uint32_t chunk,
-                                              int lane, bool all_fail) {
+                                              int lane) {
   using G = Geo<N, NV, LS, MODE>;
   const int fl = __builtin_ctzll(bal);
   const uint32_t j = __builtin_ctz(fail | 0x80000000u);
-  // an all-fail program (BOT) fails first at world 0; its accumulator is not set
+  // the least world where the program is false (world 0 for an all-fail
+  // program, whose accumulator is zero)
   uint32_t world = 0;
-  if (!all_fail) {
 #pragma unroll
-    for (int w = N - 1; w >= 0; --w)
-      if (!((c.acc[s][w] >> j) & 1u)) world = w;
-  }
+  for (int w = N - 1; w >= 0; --w)
+    if (!((c.acc[s][w] >> j) & 1u)) world = w;
   // list mode: the key's frame field is the list position, and the set is a
   // valuation field
   const uint64_t pos = G::LIST ? blk
@@ -600,7 +599,14 @@ void census_fast(FastArgs a) {
     // TOP holds everywhere: no countermodel, nothing to scan.  BOT fails at
     // world 0 of every model: every block is all-fail without interpretation.
     if (first == (uint64_t)(U_LOAD + L_TOP)) continue;
+    // BOT is false everywhere: no interpretation, a zero accumulator
     const bool all_fail = first == (uint64_t)(U_LOAD + L_BOT);
+    if (all_fail) {
+#pragma unroll
+      for (int s = 0; s < G::S; ++s)
+#pragma unroll
+        for (int w = 0; w < N; ++w) c.acc[s][w] = 0u;
+    }
 
     uint32_t cnt0 = 0;
     uint32_t* ccls = &scls[threadIdx.x >> 6][0][lane];  // class k at ccls[(k - 1) * 64]
@@ -680,7 +686,7 @@ void census_fast(FastArgs a) {
           uint32_t all = ~0u;
 #pragma unroll
           for (int w = 0; w < N; ++w) all &= c.acc[s][w];
-          uint32_t fail = all_fail ? ~0u : ~all;
+          uint32_t fail = ~all;  // an all-fail program's accumulator is zero
           if (ragged) {
             const uint64_t pos = pbase | ((uint64_t)s << G::LF) | lane_pos;
             if (pos < a.pos_begin || pos >= a.pos_end) fail = 0;
@@ -688,36 +694,50 @@ void census_fast(FastArgs a) {
           return fail;
         };
         uint32_t anyfail = 0;
+        // the common block (no range edge, no frame of a narrower class, no
+        // validity map) tests its uniform conditions once, not per set
+        const bool plain = !ragged && !classy && !(kMaps && a.valid_bits);
+        if (plain) {
 #pragma unroll
-        for (int s = 0; s < G::S; ++s) {
-          const uint32_t fail = fail_of(s);
-          cnt0 += __builtin_popcount(fail);
-          if constexpr (kMaps) {
-            if (a.valid_bits) {
-              // a frame's valuations fill 2^LV consecutive lanes: it is valid
-              // iff none of them holds a failing bit
-              const uint64_t bal = __ballot(fail != 0);
-              constexpr uint64_t kGroup = G::LV == 6 ? ~0ull : (1ull << (1 << G::LV)) - 1;
-              uint32_t inv = 0;
+          for (int s = 0; s < G::S; ++s) {
+            uint32_t all = ~0u;
 #pragma unroll
-              for (int g = 0; g < (1 << G::LF); ++g)
-                if ((bal >> (g << G::LV)) & kGroup) inv |= 1u << g;
-              vbits |= (~inv & ((1u << (1 << G::LF)) - 1u)) << (s << G::LF);
-            }
+            for (int w = 0; w < N; ++w) all &= c.acc[s][w];
+            cnt0 += __builtin_popcount(~all);
+            anyfail |= ~all;
           }
-          anyfail |= fail;
-          if constexpr (FUSED) {
-            if (classy) {
-              const uint32_t lvl = (lvl_word >> (2 * ((s << G::LF) | lane_pos))) & 3u;
+        } else {
 #pragma unroll
-              for (int k = 1; k < NC; ++k) {
-                const uint32_t fk = lvl >= (uint32_t)k ? fail : 0u;
-                ccls[(k - 1) * 64] += __builtin_popcount(fk);
-                if (key[k] == ~0ull) {
-                  const uint64_t bal = __ballot(fk != 0);
-                  if (bal) {
-                    const uint64_t kk = candidate(c, s, fk, bal, blk, chunk, lane, all_fail);
-                    best[k] = kk < best[k] ? kk : best[k];
+          for (int s = 0; s < G::S; ++s) {
+            const uint32_t fail = fail_of(s);
+            cnt0 += __builtin_popcount(fail);
+            if constexpr (kMaps) {
+              if (a.valid_bits) {
+                // a frame's valuations fill 2^LV consecutive lanes: it is valid
+                // iff none of them holds a failing bit
+                const uint64_t bal = __ballot(fail != 0);
+                constexpr uint64_t kGroup = G::LV == 6 ? ~0ull : (1ull << (1 << G::LV)) - 1;
+                uint32_t inv = 0;
+#pragma unroll
+                for (int g = 0; g < (1 << G::LF); ++g)
+                  if ((bal >> (g << G::LV)) & kGroup) inv |= 1u << g;
+                vbits |= (~inv & ((1u << (1 << G::LF)) - 1u)) << (s << G::LF);
+              }
+            }
+            anyfail |= fail;
+            if constexpr (FUSED) {
+              if (classy) {
+                const uint32_t lvl = (lvl_word >> (2 * ((s << G::LF) | lane_pos))) & 3u;
+#pragma unroll
+                for (int k = 1; k < NC; ++k) {
+                  const uint32_t fk = lvl >= (uint32_t)k ? fail : 0u;
+                  ccls[(k - 1) * 64] += __builtin_popcount(fk);
+                  if (key[k] == ~0ull) {
+                    const uint64_t bal = __ballot(fk != 0);
+                    if (bal) {
+                      const uint64_t kk = candidate(c, s, fk, bal, blk, chunk, lane);
+                      best[k] = kk < best[k] ? kk : best[k];
+                    }
                   }
                 }
               }
@@ -735,7 +755,7 @@ void census_fast(FastArgs a) {
               const uint32_t fail = fail_of(s);
               const uint64_t bal = __ballot(fail != 0);
               if (bal) {
-                const uint64_t k = candidate(c, s, fail, bal, blk, chunk, lane, all_fail);
+                const uint64_t k = candidate(c, s, fail, bal, blk, chunk, lane);
                 best[0] = k < best[0] ? k : best[0];
                 found = true;
               }
