@@ -425,3 +425,36 @@ def test_split_symmetric_and_empty(kr):
     assert (a == b).all()
     same = kr.split([(fs[0], fs[0])], frames, 6, 2)
     assert int(same[0]) == NONE
+
+
+# ------------------------------------------------------ literal pairs
+def _literal_pair_formulas():
+    """Every AND / OR of two literals over p, q (either one negated), alone, under BOX
+    and DIA, and as the operand of a further connective."""
+    lits = [[I.VAR0], [I.var(1)], [I.VAR0, I.NOT], [I.var(1), I.NOT]]
+    out = []
+    for a in lits:
+        for b in lits:
+            for op in (I.AND, I.OR):
+                f = a + b + [op]
+                out += [f, f + [I.BOX], f + [I.DIA], [I.var(1), I.DIA] + f + [I.AND]]
+    return out
+
+
+@pytest.mark.parametrize("n,cls", [(3, 0), (4, 0), (4, 1), (4, 2)])
+def test_literal_pairs(kr, orc, n, cls):
+    fs = _literal_pair_formulas()
+    keys, cnts = kr.census(fs, n, cls, 2)
+    ek, ec = _oracle_all(orc, fs, n, cls, 2, threads=4)
+    bad = [I.to_text(f) for f, k, c, a, b in zip(fs, keys, cnts, ek, ec) if k != a or c != b]
+    assert not bad, bad
+
+
+def test_literal_pairs_split(kr, orc):
+    fs = _literal_pair_formulas()
+    pairs = list(zip(fs[0::2], fs[1::2])) + list(zip(fs[1::2], fs[2::2]))
+    frames = I.frame_family(6, 300)
+    keys = kr.split(pairs, frames, 6, 2)
+    exp = _par(lambda ab: orc.split(ab[0], ab[1], frames, 2), pairs)
+    bad = [(I.to_text(a), I.to_text(b)) for (a, b), k, e in zip(pairs, keys, exp) if int(k) != e]
+    assert not bad, bad
