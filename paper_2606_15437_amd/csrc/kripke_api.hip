@@ -38,7 +38,7 @@ int fail(int code, const std::string& msg) {
 
 // ------------------------------------------------------------ batches
 struct MicroBatch {
-  std::vector<uint8_t> code;      // programs padded to 4 bytes
+  std::vector<uint8_t> code;      // programs, each padded to 8 bytes with U_END
   std::vector<uint32_t> off;      // [count + 1]
   std::vector<uint32_t> order;    // costliest first
   std::vector<int> is_const;
