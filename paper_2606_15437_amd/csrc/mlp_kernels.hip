@@ -74,6 +74,7 @@ struct PairCols {
   const uint64_t* pairs;
   uint32_t npairs;
   __device__ __forceinline__ bf16x8 load(uint32_t f, uint32_t k0) const {
+    if (f >= kIn) return as_bf16x8(u16x8(0));
     const uint32_t k = f & 4095u, w = k >> 6, sh = k & 63u;
     uint32_t byte = 0;
 #pragma unroll
@@ -131,32 +132,52 @@ struct EpiStore {  // plain fp32 row-major
 };
 
 // ---------------------------------------------------------------- GEMM
-// Block = 4 waves = a 64x64 tile of C; each wave one 32x32 MFMA tile.
-// Lane l supplies A(row = l % 32, k = k0 + 8 (l / 32) .. +7) and likewise B;
-// accumulator register r of lane l is C(8 (r / 4) + 4 (l / 32) + r % 4, l % 32).
+// Block = 4 waves = a 128x128 tile of C; each wave a 64x64 tile, i.e. 2x2
+// MFMA tiles of 32x32, so every operand fragment it loads (or expands from
+// signature bits) feeds two MFMAs.  Lane l supplies A(row = l % 32,
+// k = k0 + 8 (l / 32) .. +7) for each of its two row tiles and likewise B;
+// accumulator register r of lane l is C(8 (r / 4) + 4 (l / 32) + r % 4, l % 32)
+// of its tile.  Every element accumulates the same MFMA sequence over k as
+// with one tile per wave, so results do not depend on the tiling.
 template <class LA, class LB, class EPI>
 __global__ __launch_bounds__(256) void gemm_nt(LA A, LB B, EPI E, uint32_t M, uint32_t N,
                                                 uint32_t K) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const uint32_t m0 = blockIdx.x * 64 + (wv & 1) * 32, n0 = blockIdx.y * 64 + (wv >> 1) * 32;
-  const uint32_t ra = m0 + (lane & 31), rb = n0 + (lane & 31), kh = 8 * (lane >> 5);
-  f32x16 acc = {0};
+  const uint32_t m0 = blockIdx.x * 128 + (wv & 1) * 64, n0 = blockIdx.y * 128 + (wv >> 1) * 64;
+  const uint32_t kh = 8 * (lane >> 5);
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{0};
   for (uint32_t k0 = 0; k0 < K; k0 += 16) {
-    const bf16x8 a = A.load(ra, k0 + kh);
-    const bf16x8 b = B.load(rb, k0 + kh);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    bf16x8 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = A.load(m0 + 32 * i + (lane & 31), k0 + kh);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b[j] = B.load(n0 + 32 * j + (lane & 31), k0 + kh);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
   }
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const uint32_t m = m0 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4), n = n0 + (lane & 31);
-    if (m < M && n < N) E.store(m, n, acc[r]);
-  }
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const uint32_t m = m0 + 32 * i + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+        const uint32_t n = n0 + 32 * j + (lane & 31);
+        if (m < M && n < N) E.store(m, n, acc[i][j][r]);
+      }
 }
 
 template <class LA, class LB, class EPI>
 hipError_t gemm(LA A, LB B, EPI E, uint32_t M, uint32_t N, uint32_t K, hipStream_t s) {
   if (M == 0 || N == 0) return hipSuccess;
-  dim3 grid((M + 63) / 64, (N + 63) / 64);
+  dim3 grid((M + 127) / 128, (N + 127) / 128);
   hipLaunchKernelGGL((gemm_nt<LA, LB, EPI>), grid, dim3(256), 0, s, A, B, E, M, N, K);
   return hipGetLastError();
 }
