@@ -176,12 +176,26 @@ __global__ __launch_bounds__(256) void gemm_nt(LA A, LB B, EPI E, uint32_t M, ui
 }
 
 // TM x TN MFMA tiles per wave (block tile 64 TM x 64 TN)
-template <int TM = 2, int TN = 2, class LA, class LB, class EPI>
-hipError_t gemm(LA A, LB B, EPI E, uint32_t M, uint32_t N, uint32_t K, hipStream_t s) {
-  if (M == 0 || N == 0) return hipSuccess;
+template <int TM, int TN, class LA, class LB, class EPI>
+hipError_t gemm_tiles(LA A, LB B, EPI E, uint32_t M, uint32_t N, uint32_t K, hipStream_t s) {
   dim3 grid((M + 64 * TM - 1) / (64 * TM), (N + 64 * TN - 1) / (64 * TN));
   hipLaunchKernelGGL((gemm_nt<LA, LB, EPI, TM, TN>), grid, dim3(256), 0, s, A, B, E, M, N, K);
   return hipGetLastError();
+}
+
+// Larger per-wave tiles reuse each operand fragment for more MFMAs but make
+// fewer blocks: they are used only while the grid still has at least four
+// blocks per CU (training batches of a few hundred pairs keep one tile per
+// wave).  Every element accumulates the same MFMA sequence either way.
+template <int TM = 2, int TN = 2, class LA, class LB, class EPI>
+hipError_t gemm(LA A, LB B, EPI E, uint32_t M, uint32_t N, uint32_t K, hipStream_t s) {
+  if (M == 0 || N == 0) return hipSuccess;
+  auto blocks = [&](uint32_t tm, uint32_t tn) {
+    return (uint64_t)((M + 64 * tm - 1) / (64 * tm)) * ((N + 64 * tn - 1) / (64 * tn));
+  };
+  if (blocks(TM, TN) >= 1024) return gemm_tiles<TM, TN>(A, B, E, M, N, K, s);
+  if (blocks(2, 2) >= 1024) return gemm_tiles<2, 2>(A, B, E, M, N, K, s);
+  return gemm_tiles<1, 1>(A, B, E, M, N, K, s);
 }
 
 // ------------------------------------------------------------ small ops
