@@ -624,11 +624,14 @@ void census_fast(FastArgs a) {
       uint64_t base;
       if constexpr (G::LIST) {
         // the list frame's successor rows, wave-uniform
+        // the list is read-only for the kernel's lifetime: reading it through
+        // the constant address space gives scalar loads straight into SGPRs
+        // instead of a vector load and a wait on every frame
+        const __attribute__((address_space(4))) uint32_t* rows =
+            (const __attribute__((address_space(4))) uint32_t*)(uintptr_t)(a.list_succ + blk * N);
         base = 0;
 #pragma unroll
-        for (int w = 0; w < N; ++w)
-          base |= (uint64_t)__builtin_amdgcn_readfirstlane(a.list_succ[blk * N + w])
-                  << (w * N);
+        for (int w = 0; w < N; ++w) base |= (uint64_t)rows[w] << (w * N);
       } else {
         base = MODE == 0 ? pbase : refl_frame(pbase, N);
       }
