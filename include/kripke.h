@@ -95,8 +95,12 @@ int kripke_census(const uint8_t *code, const uint32_t *offsets, uint32_t nformul
  * kripke_census_range -- the same census restricted to raw frame indices in
  * [frame_begin, frame_end) (frames outside the class are skipped), so a
  * census can be sliced, checkpointed and resumed: merging slices with
- * min(first_key) and sum(fail_count) equals the one-shot result.
- * flags: KRIPKE_COUNT or KRIPKE_DECIDE.  1 <= n <= 6.
+ * min(first_key) and sum(fail_count) equals the one-shot result.  This is the
+ * scan of Section 5's bounded decision (Theorem 2) restricted to part of one
+ * layer; with KRIPKE_DECIDE it stops at the first countermodel, the witness
+ * Theorem 2 (2) asks for.
+ * flags: KRIPKE_COUNT or KRIPKE_DECIDE.  1 <= n <= 6 (S4 and S5: n <= 5).
+ * d_out: device array of nformulas results, overwritten.
  */
 int kripke_census_range(const uint8_t *code, const uint32_t *offsets, uint32_t nformulas,
                         uint32_t n, uint32_t cls, uint32_t nvars, uint64_t frame_begin,
@@ -122,9 +126,11 @@ int kripke_frame_validity(const uint8_t *code, const uint32_t *offsets, uint32_t
  * succ[w] set iff w R v), scanning positions in order, then valuations, then
  * worlds.  *d_first_key (device, 1 value) receives
  * position << (nvars*n + 4) | val << 4 | world, or KRIPKE_NO_KEY.
- * Limits: 1 <= n <= 10; nvars <= 4 (<= 3 for n >= 7, <= 1 for n >= 9); the
- * key must fit 64 bits (bits for the position + nvars*n + 4 <= 64);
- * otherwise KRIPKE_ELIMIT.
+ * Limits: 1 <= n <= 16; nvars <= 4, nvars <= 3 for n >= 7, and
+ * nvars * n <= 24 for n >= 9; the key must fit 64 bits (bits for the
+ * position + nvars*n + 4 <= 64); otherwise KRIPKE_ELIMIT.  Frames of 11 or
+ * more worlds (and of 9 or 10 worlds with two or more variables) run on a
+ * per-lane world-mask kernel, the others on the bit-sliced kernels.
  */
 int kripke_split(const uint8_t *phi, uint32_t len_phi, const uint8_t *psi, uint32_t len_psi,
                  const uint32_t *d_frames, uint64_t nframes, uint32_t n, uint32_t nvars,
@@ -139,7 +145,9 @@ int kripke_split_batch(const uint8_t *code, const uint32_t *offsets, uint32_t np
                        const uint32_t *d_frames, uint64_t nframes, uint32_t n, uint32_t nvars,
                        uint64_t *d_first_key, void *stream);
 
-/* Key and frame codecs (host-only, no device work). */
+/* Key and frame codecs (host-only, no device work): the successor-mask
+ * encoding of a labelled frame and the packed (frame, valuation, world)
+ * countermodel of Section 3's bitmask model (world sets as n-bit masks). */
 void kripke_key_decode(uint64_t key, uint32_t n, uint32_t nvars, uint64_t *frame,
                        uint64_t *valuation, uint32_t *world);
 void kripke_frame_decode(uint64_t frame, uint32_t n, uint32_t *succ /* [n] */);
@@ -149,7 +157,10 @@ void kripke_frame_decode(uint64_t frame, uint32_t n, uint32_t *succ /* [n] */);
  * for every class in class_mask (bit c = kripke_class c) in ONE persistent
  * launch that enumerates K frames once and reduces each frame into every
  * class containing it, captured in a hipGraph on first launch and replayed
- * afterwards.  tune_cache: path of a JSON file of autotuned tile choices
+ * afterwards.  This is Section 4's fused corpus scan (the whole batch in one
+ * kernel with per-formula reductions, compared there with separate launches
+ * per formula).  n <= 5, nformulas >= 1; the plan owns its device copies and
+ * must be destroyed with kripke_plan_destroy.  tune_cache: path of a JSON file of autotuned tile choices
  * (frame sets per lane, work items per wave).  NULL uses the defaults; with
  * a path, a cached choice for this device, n, nvars and batch is reused, and
  * otherwise every candidate is timed on a slice of the frames at creation
@@ -172,7 +183,8 @@ int kripke_plan_destroy(void *plan);
  * The library compiles every formula into an equivalent program by exact
  * rewrites (constant folding, negation normal form, operand ordering); this
  * reports, per formula, the work one evaluation of the compiled program
- * performs.  stats: int32[nformulas][6] =
+ * performs, in the terms of Proposition 2's cost bound (Boolean and modal
+ * operators).  stats: int32[nformulas][6] =
  *   {modal ops, binary ops, leaf loads, stack saves, stack slots, constant}
  * where constant is 1/0 if the formula folds to TOP/BOT, else -1.
  */
@@ -182,7 +194,8 @@ int kripke_program_stats(const uint8_t *code, const uint32_t *offsets, uint32_t 
 /*
  * kripke_calibrate_int32 -- measured rate of plain 32-bit bitwise vector
  * instructions on the current device (lane-operations per second), the
- * ceiling the evaluator is compared against.  Runs synchronously (about
+ * ceiling the evaluator is compared against (Section 8's integer calibration:
+ * dependent XOR/AND/OR chains).  Runs synchronously (about
  * 50 ms) on `stream`.
  */
 int kripke_calibrate_int32(double *lane_ops_per_s, void *stream);

@@ -52,17 +52,20 @@ def _census_status(kr, code, n=3, cls=0, nvars=2, out=C.c_void_p(16)):
 
 def test_validation_errors_without_gpu(kr):
     # every case below is rejected on the host before any device call
-    assert _census_status(kr, [99]) == -2
-    assert _census_status(kr, [I.AND]) == -2
-    assert _census_status(kr, [I.TOP, I.TOP]) == -2
-    assert _census_status(kr, [I.var(3)], nvars=2) == -2
-    assert _census_status(kr, [I.TOP] * 256) == -3
-    assert _census_status(kr, [I.TOP], n=0) == -3
-    assert _census_status(kr, [I.TOP], n=6) == -3
-    assert _census_status(kr, [I.TOP], nvars=5) == -3
-    assert _census_status(kr, [I.TOP], cls=4) == -1
-    assert _census_status(kr, [I.TOP], out=None) == -1
-    assert b"opcode" in kr.lib().kripke_last_error() or True
+    # (status, words the thread-local message must contain)
+    cases = [(dict(code=[99]), -2, b"unknown opcode 99"),
+             (dict(code=[I.AND]), -2, b"stack underflow"),
+             (dict(code=[I.TOP, I.TOP]), -2, b"leaves 2 values"),
+             (dict(code=[I.var(3)], nvars=2), -2, b"p_3"),
+             (dict(code=[I.TOP] * 256), -3, b"length"),
+             (dict(code=[I.TOP], n=0), -3, b"1 <= n <= 5"),
+             (dict(code=[I.TOP], n=6), -3, b"1 <= n <= 5"),
+             (dict(code=[I.TOP], nvars=5), -3, b"nvars"),
+             (dict(code=[I.TOP], cls=4), -1, b"class"),
+             (dict(code=[I.TOP], out=None), -1, b"null output")]
+    for kw, status, words in cases:
+        assert _census_status(kr, **kw) == status, kw
+        assert words in kr.lib().kripke_last_error(), (kw, kr.lib().kripke_last_error())
 
 
 def test_split_and_validity_limits_without_gpu(kr):
