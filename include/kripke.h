@@ -54,6 +54,7 @@ extern "C" {
 #define KRIPKE_ELIMIT (-3)   /* n, nvars, key width or program length limits  */
 #define KRIPKE_EHIP (-4)     /* a HIP runtime call failed                      */
 #define KRIPKE_ENOMEM (-5)   /* device or host allocation failed               */
+#define KRIPKE_EINTERNAL (-6) /* an internal consistency check failed          */
 
 #define KRIPKE_NO_KEY UINT64_MAX
 
@@ -167,9 +168,14 @@ void kripke_frame_decode(uint64_t frame, uint32_t n, uint32_t *succ /* [n] */);
  * and the winner is appended to the file.
  * d_out: device array [4][nformulas] (class-major); rows of classes not in
  * class_mask are left untouched.
- * KRIPKE_PLAN_PLAIN in class_mask selects the unbatched baseline instead:
- * the same kernels launched once per formula (per class), default tiles, no
- * graph -- the "separate launches" form the batched plan is compared with.
+ * Every tile candidate the autotuner times must give identical results on
+ * its frame slice; otherwise creation fails with KRIPKE_EINTERNAL.
+ * KRIPKE_PLAN_PLAIN in class_mask selects an unbatched baseline instead, no
+ * graph -- the "separate launches" form the batched plan is compared with:
+ * with tune_cache NULL, the per-class kernels launched once per formula and
+ * class with default tiles; with a tune_cache (class_mask 0xF), the fused
+ * all-class kernel launched once per formula with tiles autotuned for that
+ * form (cached under its own key).
  */
 #define KRIPKE_PLAN_PLAIN 0x10u
 int kripke_plan_create(const uint8_t *code, const uint32_t *offsets, uint32_t nformulas,

@@ -11,6 +11,7 @@
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/kripke.h"
@@ -47,20 +48,22 @@ struct MicroBatch {
   std::vector<int> slots;         // stack slots per formula
 };
 
-int compile_batch(const uint8_t* code, const uint32_t* offsets, uint32_t count, uint32_t nvars,
-                  int n, bool pairs, MicroBatch* mb) {
-  if (!code || !offsets) return fail(KRIPKE_EINVAL, "null code/offsets");
-  if (offsets[0] != 0) return fail(KRIPKE_EINVAL, "offsets[0] must be 0");
-  const uint32_t progs = pairs ? 2 * count : count;
-  for (uint32_t i = 0; i < progs; ++i)
-    if (offsets[i + 1] < offsets[i]) return fail(KRIPKE_EINVAL, "offsets must be non-decreasing");
-  mb->code.clear();
-  mb->off.assign(1, 0);
-  mb->is_const.clear();
-  mb->slots.clear();
-  mb->max_slots = 0;
-  std::vector<uint64_t> cost(count);
-  for (uint32_t i = 0; i < count; ++i) {
+// Compile programs [lo, hi) of a batch into a part of a MicroBatch (micro-op
+// code with local offsets).  Runs on worker threads: it reports a failure
+// through rc/err instead of the thread-local error slot.
+struct BatchPart {
+  std::vector<uint8_t> code;
+  std::vector<uint32_t> end;  // end offset of each program within `code`
+  std::vector<int> is_const, slots;
+  std::vector<uint64_t> cost;
+  int max_slots = 0;
+  int rc = KRIPKE_OK;
+  std::string err;
+};
+
+void compile_part(const uint8_t* code, const uint32_t* offsets, uint32_t lo, uint32_t hi,
+                  uint32_t nvars, int n, bool pairs, BatchPart* part) {
+  for (uint32_t i = lo; i < hi; ++i) {
     Compiled c;
     std::string err;
     int rc;
@@ -70,21 +73,71 @@ int compile_batch(const uint8_t* code, const uint32_t* offsets, uint32_t count, 
     } else {
       rc = compile_program(code + offsets[i], offsets[i + 1] - offsets[i], nvars, &c, &err);
     }
-    if (rc != KRIPKE_OK)
-      return fail(rc, (pairs ? "pair " : "formula ") + std::to_string(i) + ": " + err);
-    // the kernels stage each program in a fixed per-wave LDS slot
-    if (c.micro.size() + 3 > (size_t)kMaxMicro)
-      return fail(KRIPKE_ELIMIT, (pairs ? "pair " : "formula ") + std::to_string(i) +
-                                     ": compiled program too long");
-    mb->code.insert(mb->code.end(), c.micro.begin(), c.micro.end());
-    while (mb->code.size() % 8) mb->code.push_back(U_END);  // kernels fetch 8 ops at a time
-    mb->off.push_back((uint32_t)mb->code.size());
-    mb->is_const.push_back(c.is_const);
-    mb->max_slots = std::max(mb->max_slots, c.slots);
-    mb->slots.push_back(c.slots);
-    cost[i] = (uint64_t)c.modal * n * n + (uint64_t)(c.binary + c.loads + c.saves) * n + 8;
-    mb->cost_total += cost[i];
+    if (rc == KRIPKE_OK && c.micro.size() + 3 > (size_t)kMaxMicro) {
+      // the kernels stage each program in a fixed per-wave LDS slot
+      rc = KRIPKE_ELIMIT;
+      err = "compiled program too long";
+    }
+    if (rc != KRIPKE_OK) {
+      part->rc = rc;
+      part->err = (pairs ? "pair " : "formula ") + std::to_string(i) + ": " + err;
+      return;
+    }
+    part->code.insert(part->code.end(), c.micro.begin(), c.micro.end());
+    while (part->code.size() % 8) part->code.push_back(U_END);  // kernels fetch 8 ops at a time
+    part->end.push_back((uint32_t)part->code.size());
+    part->is_const.push_back(c.is_const);
+    part->max_slots = std::max(part->max_slots, c.slots);
+    part->slots.push_back(c.slots);
+    part->cost.push_back((uint64_t)c.modal * n * n + (uint64_t)(c.binary + c.loads + c.saves) * n +
+                         8);
   }
+}
+
+int compile_batch(const uint8_t* code, const uint32_t* offsets, uint32_t count, uint32_t nvars,
+                  int n, bool pairs, MicroBatch* mb) {
+  if (!code || !offsets) return fail(KRIPKE_EINVAL, "null code/offsets");
+  if (offsets[0] != 0) return fail(KRIPKE_EINVAL, "offsets[0] must be 0");
+  const uint32_t progs = pairs ? 2 * count : count;
+  for (uint32_t i = 0; i < progs; ++i)
+    if (offsets[i + 1] < offsets[i]) return fail(KRIPKE_EINVAL, "offsets must be non-decreasing");
+  // large batches compile on several host threads, each over a contiguous
+  // range; the parts are joined in order, so the result does not depend on
+  // the thread count
+  const uint32_t hw = std::max(1u, std::thread::hardware_concurrency());
+  const uint32_t nparts = count >= 8192 ? std::min<uint32_t>(std::min<uint32_t>(hw, 32),
+                                                             count / 4096)
+                                        : 1;
+  std::vector<BatchPart> parts(nparts);
+  if (nparts == 1) {
+    compile_part(code, offsets, 0, count, nvars, n, pairs, &parts[0]);
+  } else {
+    std::vector<std::thread> th;
+    for (uint32_t t = 0; t < nparts; ++t)
+      th.emplace_back(compile_part, code, offsets, (uint32_t)((uint64_t)count * t / nparts),
+                      (uint32_t)((uint64_t)count * (t + 1) / nparts), nvars, n, pairs, &parts[t]);
+    for (auto& x : th) x.join();
+  }
+  for (const BatchPart& part : parts)  // the first failing program in batch order
+    if (part.rc != KRIPKE_OK) return fail(part.rc, part.err);
+  mb->code.clear();
+  mb->off.assign(1, 0);
+  mb->is_const.clear();
+  mb->slots.clear();
+  mb->max_slots = 0;
+  mb->cost_total = 0;
+  std::vector<uint64_t> cost;
+  cost.reserve(count);
+  for (const BatchPart& part : parts) {
+    const uint32_t base = (uint32_t)mb->code.size();
+    mb->code.insert(mb->code.end(), part.code.begin(), part.code.end());
+    for (uint32_t e : part.end) mb->off.push_back(base + e);
+    mb->is_const.insert(mb->is_const.end(), part.is_const.begin(), part.is_const.end());
+    mb->slots.insert(mb->slots.end(), part.slots.begin(), part.slots.end());
+    mb->max_slots = std::max(mb->max_slots, part.max_slots);
+    cost.insert(cost.end(), part.cost.begin(), part.cost.end());
+  }
+  for (uint64_t c : cost) mb->cost_total += c;
   mb->order.resize(count);
   std::iota(mb->order.begin(), mb->order.end(), 0u);
   std::stable_sort(mb->order.begin(), mb->order.end(),
@@ -453,6 +506,20 @@ int upload_order(const Tiering& t, uint32_t* d_order, hipStream_t s) {
 
 }  // namespace
 
+static int check_range_args(uint32_t nformulas, uint32_t n, uint32_t cls, uint32_t nvars,
+                     uint64_t frame_begin, uint64_t frame_end, uint32_t flags,
+                     const kripke_census_result* d_out) {
+  if (nformulas == 0 || !d_out) return fail(KRIPKE_EINVAL, "empty batch or null output");
+  if (cls > KRIPKE_S5) return fail(KRIPKE_EINVAL, "unknown frame class");
+  if (flags > KRIPKE_DECIDE) return fail(KRIPKE_EINVAL, "unknown flags");
+  int rc = check_sizes(n, nvars, 6);
+  if (rc) return rc;
+  const uint64_t nframes = 1ull << (n * n);
+  if (frame_begin > frame_end || frame_end > nframes)
+    return fail(KRIPKE_EINVAL, "frame range outside [0, 2^(n*n))");
+  return KRIPKE_OK;
+}
+
 // ================================================================= C ABI
 extern "C" {
 
@@ -478,14 +545,8 @@ int kripke_census_range(const uint8_t* code, const uint32_t* offsets, uint32_t n
                         uint64_t frame_end, uint32_t flags, kripke_census_result* d_out,
                         void* stream) {
   g_err.clear();
-  if (nformulas == 0 || !d_out) return fail(KRIPKE_EINVAL, "empty batch or null output");
-  if (cls > KRIPKE_S5) return fail(KRIPKE_EINVAL, "unknown frame class");
-  if (flags > KRIPKE_DECIDE) return fail(KRIPKE_EINVAL, "unknown flags");
-  int rc = check_sizes(n, nvars, 6);
+  int rc = check_range_args(nformulas, n, cls, nvars, frame_begin, frame_end, flags, d_out);
   if (rc) return rc;
-  const uint64_t nframes = 1ull << (n * n);
-  if (frame_begin > frame_end || frame_end > nframes)
-    return fail(KRIPKE_EINVAL, "frame range outside [0, 2^(n*n))");
   MicroBatch mb;
   if ((rc = compile_batch(code, offsets, nformulas, nvars, (int)n, false, &mb))) return rc;
   DeviceState* ds = nullptr;
@@ -681,9 +742,28 @@ struct KripkePlan {
 static int plan_enqueue(KripkePlan* p, kripke_census_result* d_out, hipStream_t s,
                         uint64_t frames);
 
-// The unbatched baseline: per class, one (init, census) launch pair per
-// formula, each restricted to that formula through a one-entry order slice.
-static int plan_enqueue_plain(KripkePlan* p, kripke_census_result* d_out, hipStream_t s) {
+// The unbatched baselines, one launch (pair) per formula, each restricted to
+// that formula through a one-entry slice of the order array:
+//   - plain (p->ls < 0): per class, an (init, census) pair per formula with
+//     the default tiles;
+//   - per-formula + autotuned (p->ls >= 0): the fused all-class kernel with
+//     the tuned tiles, one launch per formula, over frames [0, frames) (0 =
+//     all), so only batching separates it from the batched plan.
+static int plan_enqueue_plain(KripkePlan* p, kripke_census_result* d_out, hipStream_t s,
+                              uint64_t frames = 0) {
+  if (p->ls >= 0) {
+    const uint64_t nf = frames ? frames : 1ull << (p->n * p->n);
+    auto* key = reinterpret_cast<unsigned long long*>(&d_out[0].first_key);
+    auto* cnt = reinterpret_cast<unsigned long long*>(&d_out[0].fail_count);
+    KR_HIP(launch_init(key, cnt, 2, 4 * p->nformulas, nullptr, s));
+    for (uint32_t i = 0; i < p->nformulas; ++i) {
+      const int ls = i < p->tiers.count_a ? p->tiers.ls_a : p->tiers.ls_b;
+      int rc = enqueue_fast(p->ds, p->db, p->n, p->nvars, ls, 0, true, 1, 0, nf, key, cnt, false,
+                            p->db.queue, s, p->ipw, 0, i, false, p->nformulas);
+      if (rc) return rc;
+    }
+    return KRIPKE_OK;
+  }
   for (int c = 0; c < 4; ++c) {
     if (!((p->class_mask >> c) & 1u)) continue;
     kripke_census_result* row = d_out + (size_t)c * p->nformulas;
@@ -719,6 +799,11 @@ static int plan_enqueue_plain(KripkePlan* p, kripke_census_result* d_out, hipStr
 // persistent queue).  Every candidate is timed on a prefix slice of the
 // frames; the choice is cached in a small JSON file keyed by device, shape
 // and a hash of the compiled batch.
+static int plan_enqueue_any(KripkePlan* p, kripke_census_result* d_out, hipStream_t s,
+                            uint64_t frames) {
+  return p->plain ? plan_enqueue_plain(p, d_out, s, frames) : plan_enqueue(p, d_out, s, frames);
+}
+
 static std::string tune_key(const KripkePlan* p) {
   uint64_t h = 1469598103934665603ull;
   for (uint8_t b : p->mb.code) h = (h ^ b) * 1099511628211ull;
@@ -727,8 +812,9 @@ static std::string tune_key(const KripkePlan* p) {
   hipGetDevice(&dev);
   hipGetDeviceProperties(&prop, dev);
   char buf[256];
-  snprintf(buf, sizeof buf, "%s/%dcu/n%d/v%d/m%u/B%u/h%016llx", prop.gcnArchName, p->ds->cus,
-           p->n, p->nvars, p->class_mask, p->nformulas, (unsigned long long)h);
+  snprintf(buf, sizeof buf, "%s/%dcu/n%d/v%d/m%u/B%u/h%016llx%s", prop.gcnArchName, p->ds->cus,
+           p->n, p->nvars, p->class_mask, p->nformulas, (unsigned long long)h,
+           p->plain ? "/per-formula" : "");
   for (char* c = buf; *c; ++c)
     if (*c == '"' || *c == '\\') *c = '_';
   return buf;
@@ -793,14 +879,16 @@ static int tune_plan(KripkePlan* p, const char* path) {
     p->tiers = t;
     return upload_order(t, p->db.order, p->cap);
   }
-  kripke_census_result* scratch = nullptr;
-  KR_HIP(hipMalloc(&scratch, sizeof(kripke_census_result) * 4 * p->nformulas));
+  kripke_census_result* trial_out = nullptr;
+  KR_HIP(hipMalloc(&trial_out, sizeof(kripke_census_result) * 4 * p->nformulas));
   hipEvent_t e0, e1;
   KR_HIP(hipEventCreate(&e0));
   KR_HIP(hipEventCreate(&e1));
   const uint64_t slice = std::min<uint64_t>(1ull << (p->n * p->n), 1ull << 20);
   double best = 1e300;
   int best_ls = p->ls, best_ipw = p->ipw;
+  // every candidate computes the same slice; its results must be identical
+  std::vector<kripke_census_result> first_res, res(4 * (size_t)p->nformulas);
   for (int l = 0; l <= 3; ++l) {
     if (!make_tiers(p->mb, p->n, p->nvars, 0, true, l, &t)) continue;
     p->tiers = t;
@@ -809,14 +897,25 @@ static int tune_plan(KripkePlan* p, const char* path) {
     for (int w : {4, 16, 64}) {
       p->ls = l;
       p->ipw = w;
-      int rc = plan_enqueue(p, scratch, p->cap, slice);  // warm
+      int rc = plan_enqueue_any(p, trial_out, p->cap, slice);  // warm
       if (rc) return rc;
       KR_HIP(hipEventRecord(e0, p->cap));
-      if ((rc = plan_enqueue(p, scratch, p->cap, slice))) return rc;
+      if ((rc = plan_enqueue_any(p, trial_out, p->cap, slice))) return rc;
       KR_HIP(hipEventRecord(e1, p->cap));
       KR_HIP(hipEventSynchronize(e1));
       float ms = 0;
       KR_HIP(hipEventElapsedTime(&ms, e0, e1));
+      KR_HIP(hipMemcpy(res.data(), trial_out, res.size() * sizeof(res[0]), hipMemcpyDeviceToHost));
+      if (first_res.empty()) {
+        first_res = res;
+      } else if (memcmp(first_res.data(), res.data(), res.size() * sizeof(res[0])) != 0) {
+        hipFree(trial_out);
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        return fail(KRIPKE_EINTERNAL, "autotuner: tile candidate ls=" + std::to_string(l) +
+                                          " ipw=" + std::to_string(w) +
+                                          " disagrees with the first candidate");
+      }
       if (ms < best) {
         best = ms;
         best_ls = l;
@@ -830,7 +929,7 @@ static int tune_plan(KripkePlan* p, const char* path) {
   if (int rc1 = upload_order(p->tiers, p->db.order, p->cap)) return rc1;
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  KR_HIP(hipFree(scratch));
+  KR_HIP(hipFree(trial_out));
   tune_store(path, key, best_ls, best_ipw, best);
   return KRIPKE_OK;
 }
@@ -1112,9 +1211,10 @@ int kripke_plan_create(const uint8_t* code, const uint32_t* offsets, uint32_t nf
         delete p;
         return rc;
       }
-  // tables used inside the captured graph must exist before capture
-  if (class_mask == 0xF && n <= 5 && !plain && pick_tiers(p->mb, (int)n, (int)nvars, 0, true,
-                                                            &p->tiers))
+  // tables used inside the captured graph must exist before capture; the
+  // per-formula baseline uses the fused kernel only when it is autotuned
+  if (class_mask == 0xF && n <= 5 && (!plain || tune_cache) &&
+      pick_tiers(p->mb, (int)n, (int)nvars, 0, true, &p->tiers))
     p->ls = p->tiers.ls_a;
   if (p->ls >= 0) {
     const uint32_t* lv = nullptr;

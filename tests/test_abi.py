@@ -89,3 +89,16 @@ def test_split_and_validity_limits_without_gpu(kr):
     assert valid(cp1, op1, 1, 4, 3, out, None) == -3             # n * nvars > 11
     assert valid(cp1, op1, 1, 4, 2, None, None) == -1            # output missing
     assert b"n" in kr.lib().kripke_last_error()
+
+
+def test_large_batch_reports_first_invalid_program(kr):
+    """Large batches compile on several host threads; the error still names the first
+    invalid program in batch order, and nothing reaches the device."""
+    fs = [I.parse("[]p -> <>q")] * 20000
+    fs[9000] = [I.AND]
+    fs[15000] = [99]
+    c, o = I.pack(fs)
+    cp = c.ctypes.data_as(C.POINTER(C.c_uint8))
+    op = o.ctypes.data_as(C.POINTER(C.c_uint32))
+    assert kr.lib().kripke_census(cp, op, len(fs), 3, 0, 2, C.c_void_p(16), None) == -2
+    assert kr.lib().kripke_last_error().startswith(b"formula 9000: stack underflow")
