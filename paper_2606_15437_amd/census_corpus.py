@@ -3,7 +3,7 @@
 Corpus: every constant-free formula of at most seven nodes over two variables
 (44,678 trees), one representative per class of equal truth at every pointed model
 with at most three worlds (the first member in enumeration order), plus the named
-axioms.  Census: for each formula and class K, T, S4, S5, every frame with
+axioms K, T and McKinsey.  Census: for each formula and class K, T, S4, S5, every frame with
 n = 1..5 worlds and every valuation, recording the failure count per n, the least
 countermodel at each n and the minimal countermodel size (Section 6, Proposition 4,
 Corollary 1).  Every evaluation runs in the library's kernels; n = 5 is one fused
@@ -110,12 +110,15 @@ def summary(res):
         hist[c]["none"] = int(surv[i].sum())
     sep = {"K->T": int((~surv[0] & surv[1]).sum()), "T->S4": int((~surv[1] & surv[2]).sum()),
            "S4->S5": int((~surv[2] & surv[3]).sum())}
+    # one certificate (the least countermodel at the minimal size) per refuted
+    # (formula, class) pair
+    certificates = int((~surv).sum())
     # weakest class in which each formula survives (4 = none)
     strata = np.where(surv.any(axis=0), surv.argmax(axis=0), 4)
     names = list(CLASSES) + ["none"]
     return {"minimal_size_histogram": hist, "survivors": {c: int(surv[i].sum())
                                                           for i, c in enumerate(CLASSES)},
-            "separations": sep,
+            "separations": sep, "certificates": certificates,
             "strata": {names[k]: int((strata == k).sum()) for k in range(5)},
             "max_refuted_minimal_size": {c: int(m[i].max()) for i, c in enumerate(CLASSES)}}
 

@@ -614,8 +614,9 @@ def enumerate_formulas(max_nodes: int = 7, leaves=(VAR0, VAR0 + 1)) -> list[list
 
 
 def named_axioms() -> list[list[int]]:
-    """The named axioms added to the census corpus: K (normality), T and D."""
-    return [parse("[](p -> q) -> ([]p -> []q)"), parse("[]p -> p"), parse("[]p -> <>p")]
+    """The named axioms added to the census corpus: K (normality), T and McKinsey
+    (the named control of Section 10's correspondence table)."""
+    return [parse("[](p -> q) -> ([]p -> []q)"), parse("[]p -> p"), parse("[]<>p -> <>[]p")]
 
 
 def all_pointed_models(max_n: int = 3, nvars: int = 2) -> np.ndarray:
