@@ -20,9 +20,13 @@ from . import kripke as K
 
 # ------------------------------------------------------------ the library
 def _bits(frames: np.ndarray, n: int):
-    """R(w, v) as boolean arrays over the given frame indices."""
+    """R(w, v) as boolean arrays over the given frame indices (each computed once)."""
+    cache = {}
+
     def b(w, v):
-        return ((frames >> np.uint64(w * n + v)) & np.uint64(1)).astype(bool)
+        if (w, v) not in cache:
+            cache[(w, v)] = ((frames >> np.uint64(w * n + v)) & np.uint64(1)).astype(bool)
+        return cache[(w, v)]
     return b
 
 
@@ -82,10 +86,21 @@ def library():
     return lib
 
 
-def extensions(names, max_n=4, chunk=1 << 20):
+# The conditions of the paper's correspondence table (Section 10, Table 9), in its order.
+TABLE9_CONDITIONS = ("reflexive", "serial", "transitive", "euclidean", "symmetric",
+                     "partially functional", "dense", "directed")
+
+
+def table9_library():
+    """Only the eight first-order conditions Table 9 names."""
+    base = base_conditions()
+    return {name: base[name] for name in TABLE9_CONDITIONS}
+
+
+def extensions(names, max_n=4, chunk=1 << 20, lib=None):
     """name -> boolean array over all frames with n = 1..max_n worlds (concatenated in
     order of n, then frame index)."""
-    lib = library()
+    lib = library() if lib is None else lib
     out = {name: [] for name in names}
     for n in range(1, max_n + 1):
         total = 1 << (n * n)
@@ -125,12 +140,13 @@ def validity(formulas, max_n=4, chunk=512):
     return np.concatenate(parts, axis=0)
 
 
-def recover(formulas, max_n=4, log=None):
+def recover(formulas, max_n=4, log=None, lib=None):
     """Per formula: 'trivial' (valid on all or no frames), the recovered condition
-    names, or [] (no match in the library)."""
+    names, or [] (no match in the library; `lib` defaults to library())."""
+    lib = library() if lib is None else lib
     val = validity(formulas, max_n)
-    names = list(library())
-    ext = extensions(names, max_n)
+    names = list(lib)
+    ext = extensions(names, max_n, lib=lib)
     table = {}
     for name in names:
         table.setdefault(np.packbits(ext[name]).tobytes(), []).append(name)
@@ -156,28 +172,49 @@ def table9():
     return [(name, I.parse(text)) for name, text in rows]
 
 
-def reconfirm(formulas, conditions, n=5, frames=None, chunk=1 << 20):
-    """For each (formula, condition name): Val_n(phi) == Ext_n(X) over all frames on n
-    worlds (or the given frame indices)."""
-    import torch
-    code, offs = I.pack(formulas)
-    words = ((1 << (n * n)) + 31) // 32
-    dv = torch.zeros((len(formulas), words), dtype=torch.int32, device="cuda")
-    K.kripke_frame_validity(code, offs, n, 2, dv)
-    maps = dv.cpu().numpy().view(np.uint32)
-    del dv
-    lib = library()
+def condition_maps(names, n=5, chunk=1 << 20):
+    """name -> Ext_n(X) over every frame index on n worlds as a packed bitmap (bit f % 32
+    of word f / 32, the layout of the validity maps); a conjunction "a & b" is the AND of
+    its parts' maps, each base condition is evaluated once."""
+    base = base_conditions()
+    parts = {name: name.split(" & ") for name in names}
+    need = sorted({p for ps in parts.values() for p in ps})
     total = 1 << (n * n)
-    idx = np.arange(total, dtype=np.uint64) if frames is None else np.asarray(frames, np.uint64)
-    ok = [True] * len(formulas)
-    for start in range(0, len(idx), chunk):
-        f = idx[start:start + chunk]
-        b = _bits(f, n)
-        word = (f >> np.uint64(5)).astype(np.int64)
-        bit = (f & np.uint64(31)).astype(np.uint32)
-        for i, cond in enumerate(conditions):
-            if not ok[i]:
-                continue
-            val = ((maps[i, word] >> bit) & 1).astype(bool)
-            ok[i] = bool((val == lib[cond](b, n, f.shape)).all())
+    words = (total + 31) // 32
+    out = {b: np.zeros(words, dtype=np.uint32) for b in need}
+    for start in range(0, total, chunk):
+        frames = np.arange(start, min(total, start + chunk), dtype=np.uint64)
+        bits = _bits(frames, n)
+        for b in need:
+            v = base[b](bits, n, frames.shape)
+            packed = np.packbits(v, bitorder="little")
+            packed = np.pad(packed, (0, (-len(packed)) % 4))
+            out[b][start // 32:start // 32 + len(packed) // 4] = packed.view(np.uint32)
+    res = {}
+    for name, ps in parts.items():
+        m = out[ps[0]].copy()
+        for p in ps[1:]:
+            m &= out[p]
+        res[name] = m
+    return res
+
+
+def reconfirm(formulas, conditions, n=5, batch=256, maps=None):
+    """For each (formula, condition name): Val_n(phi) == Ext_n(X) over every frame on n
+    worlds (33,554,432 at n = 5), comparing the formula's validity map from the census
+    kernel with the condition's extension bitmap.  `maps` may hold precomputed
+    condition_maps."""
+    import torch
+    ext = condition_maps(set(conditions), n) if maps is None else maps
+    words = ((1 << (n * n)) + 31) // 32
+    ok = []
+    for s in range(0, len(formulas), batch):
+        sub = formulas[s:s + batch]
+        code, offs = I.pack(sub)
+        dv = torch.zeros((len(sub), words), dtype=torch.int32, device="cuda")
+        K.kripke_frame_validity(code, offs, n, 2, dv)
+        val = dv.cpu().numpy().view(np.uint32)
+        del dv
+        for i, cond in enumerate(conditions[s:s + batch]):
+            ok.append(bool(np.array_equal(val[i], ext[cond])))
     return ok
