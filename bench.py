@@ -4,17 +4,21 @@ One step = one replay of the captured hipGraph holding the single persistent
 launch that censuses the 4,096-formula batch (2 variables, uneven lengths
 3..40, modal depth caps 0..6) over every labelled frame on 5 worlds and every
 valuation, reducing each K frame into every class (K, T, S4, S5) containing
-it.  `value` is evaluated (formula, frame, valuation) triples per second; the
-T/S4/S5 results are reductions of the same evaluations and are not counted
-again.
+it.  `value` is evaluated (formula, frame, valuation) triples per second, over
+the formulas that do not fold to a constant (those are decided without
+evaluation); the T/S4/S5 results are reductions of the same evaluations and are
+not counted again.
 
 Also reported in the JSON line:
-  - plain_vs_batched: the same census with the same kernels launched once per
-    formula and class (16,384 launches, default tiles, no graph);
+  - plain_vs_batched: the same census launched once per formula: "plain" with the
+    per-class kernels and default tiles (16,384 launches), "per_formula_autotuned" with
+    the fused all-class kernel and tiles tuned for that form (4,096 launches), no graph;
   - roofline: the census kernel against the INT32 VALU peak, counting the
     bit operations of Proposition 2 on the programs actually executed (after
     exact constant folding); the figure on the source formulas is given too;
-  - cpu_baseline: the CPU oracle on a bounded sample of the same workload;
+  - cpu_baseline: the CPU oracle on bounded samples of the n = 5 workload, the
+    Table-1 matched workload and the n = 4 three-variable subset, median of 5, on one
+    thread and on every host core;
   - table1: the paper's matched single-formula workload;
   - split: the split search (Definition 2, Proposition 5) of formula pairs that agree on
     every model with at most 4 worlds, over the 6-, 7- and 8-world frame families;
@@ -86,7 +90,7 @@ def bench_split(args, stream):
     from paper_2606_15437_amd import kripke as K
     from paper_2606_15437_amd.split_workload import config4_pairs
     t0 = time.time()
-    pairs, stats = config4_pairs(args.split_pairs, pool=50_000)
+    pairs, stats = config4_pairs(args.split_pairs, pool=args.split_pool)
     sel_s = time.time() - t0
     code, offs = I.pack([p for ab in pairs for p in ab])
     st = K.kripke_program_stats(*I.pack([I.iff(a, b) for a, b in pairs]), 2)
@@ -115,8 +119,9 @@ def bench_split(args, stream):
         log(f"split n={n}: {ms:.0f} ms, {evals / ms / 1e6:.0f} G evals/s, "
             f"{int(found.sum())} of {len(pairs)} pairs separated")
     return {"workload": f"{len(pairs)} pairs agreeing through 4 worlds ({stats['designed']} "
-                        f"designed) x first {args.split_frames} frames of the n = 6, 7, 8 "
-                        f"families x all 2^(2n) valuations",
+                        f"designed) from a pool of {args.split_pool} formulas x first "
+                        f"{args.split_frames} frames of the n = 6, 7, 8 families x all "
+                        f"2^(2n) valuations",
             "G_evals_per_s": tot_evals / tot_ms / 1e6, "ms": tot_ms, "per_n": per,
             # the dominant kernel is the n = 8 list kernel
             "roofline": {"bound": "alu", "achieved": per["8"]["T_int32_ops_per_s"],
@@ -127,6 +132,51 @@ def bench_split(args, stream):
                          "all_n_achieved": tot_ops / tot_ms / 1e9},
             "selection": dict(stats, seconds=sel_s),
             "note": "timed per call including host compile and upload of the pair programs"}
+
+
+def bench_cpu(fs, reps=5):
+    """The CPU oracle (recursive satisfaction over explicit sets) timed on the host cores,
+    on bounded samples of three workloads, median of `reps` runs, on one thread and on
+    every core (the oracle splits a frame range over threads and merges min/sum)."""
+    import statistics
+    from oracle import oracle as orc
+    from paper_2606_15437_amd import inputs as I
+    nproc = os.cpu_count()
+    # (name, formulas, n, nvars, (formulas, frames) on one thread, ... on all cores)
+    work = [
+        ("table1_matched", [I.parse(I.TABLE1_FORMULA)], 5, 2, (1, 1 << 12), (1, 1 << 16)),
+        ("c2_subset_n4_K", I.config2_formulas()[:64], 4, 3, (4, 1 << 8), (64, 1 << 8)),
+        ("c3_slice_n5_K", fs[:64], 5, 2, (8, 1 << 10), (64, 1 << 11)),
+    ]
+    out = {}
+    for name, formulas, n, nvars, one, every in work:
+        rec = {}
+        for label, (nf, frames), threads in (("single_thread", one, 1), ("all_cores", every, 0)):
+            times, used = [], 1
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                for f in formulas[:nf]:
+                    _, _, used = orc.census(f, n, 0, nvars, 0, frames, threads=threads)
+                times.append(time.perf_counter() - t0)
+            evals = float(nf) * frames * (1 << (n * nvars))
+            med = statistics.median(times)
+            rec[label] = {"G_evals_per_s": evals / med / 1e9, "threads": used,
+                          "median_s": med, "runs_s": times,
+                          "sample": f"{nf} formula(s) x frames [0, {frames}) x "
+                                    f"{1 << (n * nvars)} valuations, n = {n}, class K"}
+        out[name] = rec
+        log(f"cpu oracle {name}: {rec['single_thread']['G_evals_per_s']:.4f} G evals/s on one "
+            f"thread, {rec['all_cores']['G_evals_per_s']:.4f} on {rec['all_cores']['threads']}")
+    head = out["c3_slice_n5_K"]
+    return {"value": head["all_cores"]["G_evals_per_s"], "unit": "G evals/s",
+            "cores": head["all_cores"]["threads"], "kind": "oracle",
+            "sample": "n = 5 census workload slice: " + head["all_cores"]["sample"] +
+                      f", median of {reps} runs",
+            "single_thread_value": head["single_thread"]["G_evals_per_s"],
+            "nproc": nproc, "workloads": out,
+            "paper_context": {"cpu_scalar_1_thread": 0.0471, "cpu_bitmask_openmp_26": 0.814,
+                              "cpu_avx512_openmp_26": 5.43, "gpu_h100_table1": 38.33,
+                              "hardware": "Xeon Platinum 8480+ and H100 PCIe"}}
 
 
 def bench_learned():
@@ -145,7 +195,9 @@ def bench_reproduction():
     out["G_evals_per_s_five_world"] = out["k_frame_evals"] / out["census_seconds"] / 1e9
     out["paper"] = {"raw_trees": 44678, "classes": 5621, "formulas": 5624,
                     "K_refuted_on_1": 5086, "K_refuted_on_2": 536, "K_survivors": 2,
-                    "T->S4": 48, "S4->S5": 118, "minutes": 45, "evals": 1.63e14}
+                    "K->T": 428, "T->S4": 48, "S4->S5": 118, "certificates": 20990,
+                    "minutes": 45, "evals": 1.63e14}
+    out["named_axioms"] = "K, T, McKinsey"
     return out
 
 
@@ -160,23 +212,43 @@ def bench_synthesis():
 
 
 def bench_correspondence():
+    """Frame-correspondence recovery (Section 10) over the census corpus with two condition
+    libraries: the eight conditions Table 9 names, and our 136-condition library (16 base
+    conditions and every conjunction of two).  Every recovered (formula, condition) is
+    re-confirmed over all 33,554,432 five-world frames."""
     import collections
     from paper_2606_15437_amd import census_corpus as C
     from paper_2606_15437_amd import correspondence as R
     _, _, corpus = C.build_corpus()
-    t0 = time.time()
-    out = R.recover(corpus, max_n=4, log=log)
-    dt = time.time() - t0
-    rec = [o for o in out if isinstance(o, list) and o]
-    conds = collections.Counter(o[0] for o in rec)
-    table9 = {name: (r if r != "trivial" else "trivial")
-              for (name, _), r in zip(R.table9(), R.recover([f for _, f in R.table9()], 4))}
-    return {"formulas": len(out), "recovered": len(rec),
-            "trivial": sum(1 for o in out if o == "trivial"),
-            "unmatched": sum(1 for o in out if o == []), "seconds": dt,
-            "library_size": len(R.library()), "most_recovered": conds.most_common(8),
-            "table9": table9,
-            "paper": {"recovered": 220, "trivial": 2798, "unmatched": 2606}}
+    out = {"formulas": len(corpus),
+           "paper": {"recovered": 220, "trivial": 2798, "unmatched": 2606,
+                     "reconfirmed_on": "all 33,554,432 five-world frames"}}
+    maps = None
+    for name, lib in (("table9_conditions", R.table9_library()),
+                      ("library_136", R.library())):
+        t0 = time.time()
+        res = R.recover(corpus, max_n=4, log=log, lib=lib)
+        rec_idx = [i for i, o in enumerate(res) if isinstance(o, list) and o]
+        dt = time.time() - t0
+        # re-confirm every recovered formula with its first matching condition
+        t1 = time.time()
+        conds = [res[i][0] for i in rec_idx]
+        need = set(conds)
+        if maps is None or not need <= set(maps):
+            maps = R.condition_maps(sorted(need | set(maps or {})), 5)
+        ok = R.reconfirm([corpus[i] for i in rec_idx], conds, 5, maps=maps)
+        counts = collections.Counter(conds)
+        out[name] = {"library_size": len(lib), "recovered": len(rec_idx),
+                     "trivial": sum(1 for o in res if o == "trivial"),
+                     "unmatched": sum(1 for o in res if o == []), "seconds": dt,
+                     "reconfirmed_five_worlds": int(sum(ok)),
+                     "reconfirm_frames": 1 << 25, "reconfirm_s": time.time() - t1,
+                     "most_recovered": counts.most_common(8)}
+        log(f"correspondence ({name}): {len(rec_idx)} recovered, {int(sum(ok))} re-confirmed on "
+            f"every five-world frame ({time.time() - t1:.1f} s)")
+    rows = R.table9()
+    out["table9"] = {n: r for (n, _), r in zip(rows, R.recover([f for _, f in rows], 4))}
+    return out
 
 
 def bench_adversarial():
@@ -199,15 +271,14 @@ def main():
     ap.add_argument("--formulas", type=int, default=4096)
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2606_15437_amd",
                                                          "tune_cache.json"))
-    ap.add_argument("--cpu-frames-log2", type=int, default=14)
-    ap.add_argument("--cpu-formulas", type=int, default=64)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (reference for "
                          "HBM byte counters)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--split-pairs", type=int, default=2048)
-    ap.add_argument("--split-frames", type=int, default=65536)
+    ap.add_argument("--split-pairs", type=int, default=20_000)
+    ap.add_argument("--split-pool", type=int, default=200_000)
+    ap.add_argument("--split-frames", type=int, default=1_000_000)
     ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-reproduction", action="store_true")
@@ -254,7 +325,11 @@ def main():
         ms_w = timed(lambda: K.kripke_plan_launch(plan, out, stream), stream)
         log(f"warmup {i}: {ms_w:.0f} ms")
     ms = timed(lambda: K.kripke_plan_launch(plan, out, stream), stream, args.steps)
-    evals_step = float(B) * CLASS_FRAMES_N5[0] * nval
+    # formulas that fold to TOP or BOT are decided without evaluation (TOP is skipped,
+    # BOT fails at world 0 of every model): only the others' triples are counted
+    live = int((st[:, 5] == -1).sum())
+    evals_step = float(live) * CLASS_FRAMES_N5[0] * nval
+    evals_step_all = float(B) * CLASS_FRAMES_N5[0] * nval
     value = evals_step / (ms / 1e3)
     res = K.as_u64(out).copy()
     log(f"batched all-class step: {ms:.1f} ms, {value / 1e9:.0f} G evals/s")
@@ -267,21 +342,30 @@ def main():
     log(f"roofline: {achieved / 1e12:.2f} T INT32 ops/s executed "
         f"({100 * achieved / PEAK_INT32:.1f}% of peak)")
 
-    # ------------------------------------------------- plain: per-formula
+    # ------------------------------------------------- unbatched baselines
     plain = None
     if not args.no_plain:
-        pplan = K.kripke_plan_create(code, offs, n, 0xF | K.KRIPKE_PLAN_PLAIN, nvars)
-        out2 = torch.empty((4, B, 2), dtype=torch.int64, device=dev)
-        t0 = time.time()
-        ms_p = timed(lambda: K.kripke_plan_launch(pplan, out2, stream), stream)
-        host_s = time.time() - t0
-        K.kripke_plan_destroy(pplan)
-        same = bool((K.as_u64(out2) == res).all())
-        plain = {"ms": ms_p, "G_evals_per_s": evals_step / ms_p / 1e6, "launches": 4 * B,
-                 "batched_ms": ms, "speedup_batched": ms_p / ms, "results_identical": same,
-                 "host_s": host_s}
-        log(f"plain per-formula launches: {ms_p:.0f} ms ({ms_p / ms:.2f}x the batched step), "
-            f"identical={same}")
+        plain = {"batched_ms": ms, "launches_batched": 1}
+        for name, mask, cache in (("plain", 0xF | K.KRIPKE_PLAN_PLAIN, None),
+                                  ("per_formula_autotuned", 0xF | K.KRIPKE_PLAN_PLAIN,
+                                   args.tune_cache)):
+            t0 = time.time()
+            pplan = K.kripke_plan_create(code, offs, n, mask, nvars, tune_cache=cache)
+            create_s = time.time() - t0
+            out2 = torch.empty((4, B, 2), dtype=torch.int64, device=dev)
+            t0 = time.time()
+            ms_p = timed(lambda: K.kripke_plan_launch(pplan, out2, stream), stream)
+            host_s = time.time() - t0
+            K.kripke_plan_destroy(pplan)
+            same = bool((K.as_u64(out2) == res).all())
+            plain[name] = {"ms": ms_p, "G_evals_per_s": evals_step / ms_p / 1e6,
+                           "launches": (4 if cache is None else 1) * B,
+                           "speedup_batched": ms_p / ms, "results_identical": same,
+                           "host_s": host_s, "create_s": create_s}
+            log(f"{name}: {ms_p:.0f} ms ({ms_p / ms:.2f}x the batched step), identical={same}")
+        # the figures of the untuned form stay at the top level for continuity
+        plain.update({k: plain["plain"][k] for k in ("ms", "G_evals_per_s", "launches",
+                                                     "speedup_batched", "results_identical")})
 
     # ------------------------------------------- Table 1 matched workload
     t1 = I.parse(I.TABLE1_FORMULA)
@@ -297,29 +381,7 @@ def main():
     log(f"table-1 matched workload: {table1['G_evals_per_s']:.1f} G evals/s")
 
     # ---------------------------------------------------------- CPU oracle
-    cpu = None
-    if not args.no_cpu:
-        from oracle import oracle as orc
-        sub = fs[:args.cpu_formulas]
-        F = 1 << args.cpu_frames_log2
-        t0 = time.time()
-        threads = 0
-        for f in sub:
-            _, _, threads = orc.census(f, n, 0, nvars, 0, F, threads=0)
-        dt = time.time() - t0
-        cpu_evals = float(len(sub)) * F * nval
-        # the same oracle on one thread, over a sixty-fourth of the frames
-        t1 = time.time()
-        for f in sub:
-            orc.census(f, n, 0, nvars, 0, F // 64, threads=1)
-        single = float(len(sub)) * (F // 64) * nval / (time.time() - t1) / 1e9
-        cpu = {"value": cpu_evals / dt / 1e9, "unit": "G evals/s", "cores": threads,
-               "single_thread_value": single,
-               "kind": "oracle",
-               "sample": f"first {len(sub)} formulas of the 4,096-formula batch x frames "
-                         f"[0, 2^{args.cpu_frames_log2}) x {nval} valuations, class K "
-                         f"({cpu_evals:.3g} evaluations in {dt:.1f} s)"}
-        log(f"cpu oracle: {cpu['value']:.4f} G evals/s on {threads} threads")
+    cpu = None if args.no_cpu else bench_cpu(fs)
 
     split = None if args.no_split else bench_split(args, stream)
     learned = None if args.no_learned else bench_learned()
@@ -332,6 +394,7 @@ def main():
     rec = {
         "metric": "formula*frame*valuation G evals/s, n=5 census (batched hipGraph vs plain)",
         "value": value / 1e9,
+        "value_counting_folded_formulas": evals_step_all / (ms / 1e3) / 1e9,
         "unit": "G evals/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -346,6 +409,9 @@ def main():
                                "depth cap 0..6) x 33,554,432 frames x 1,024 valuations (2 vars), "
                                "classes K+T+S4+S5 fused in one graph-replayed launch",
                    "formulas": B, "n": n, "nvars": nvars, "evals_per_step": evals_step,
+                   "evaluated_formulas": live,
+                   "folded_formulas": {"TOP": int((st[:, 5] == 1).sum()),
+                                       "BOT": int((st[:, 5] == 0).sum())},
                    "no_countermodel_per_class": valid},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32 / 1e12,
                      "unit": "T INT32 ops/s", "frac": achieved / PEAK_INT32,

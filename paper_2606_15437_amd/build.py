@@ -59,6 +59,58 @@ def build(verbose: bool = False, force: bool = True) -> str:
     return OUT
 
 
+def resources(out_path: str, sources=None) -> str:
+    """Per-kernel register, scratch and occupancy figures as the compiler reports them
+    (device-only compile of each source with kernel resource-usage remarks), written as
+    a markdown table to out_path."""
+    import re
+    srcs = [s for s in (sources or SOURCES) if s.endswith(".hip")]
+    fields = ("TotalSGPRs", "VGPRs", "AGPRs", "ScratchSize [bytes/lane]", "LDS Size [bytes/block]",
+              "Occupancy [waves/SIMD]")
+
+    def one(src):
+        cmd = [HIPCC, *FLAGS, "--cuda-device-only", "-Rpass-analysis=kernel-resource-usage",
+               "-c", os.path.join(CSRC, src), "-o", os.devnull]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+        rows, cur = [], None
+        for line in r.stderr.splitlines():
+            m = re.search(r"remark: Function Name: (\S+)", line)
+            if m:
+                cur = {"src": src, "name": m.group(1)}
+                rows.append(cur)
+                continue
+            m = re.search(r"remark:\s+([^:]+): (\S+) \[-Rpass-analysis", line)
+            if m and cur is not None and m.group(1).strip() in fields:
+                cur[m.group(1).strip()] = m.group(2)
+        return rows
+
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        rows = [r for part in ex.map(one, srcs) for r in part]
+    names = subprocess.run(["c++filt"], input="\n".join(r["name"] for r in rows),
+                           capture_output=True, text=True).stdout.splitlines()
+    lines = ["| source | kernel | VGPRs | AGPRs | SGPRs | scratch B/lane | LDS B/block | "
+             "waves/SIMD |", "|---|---|---|---|---|---|---|---|"]
+    for r, nm in zip(rows, names):
+        nm = nm.replace("kripke::", "").replace("(anonymous namespace)::", "")
+        nm = nm.replace("|", "\\|")
+        lines.append(f"| {r['src']} | `{nm}` | {r.get('VGPRs', '?')} | {r.get('AGPRs', '?')} | "
+                     f"{r.get('TotalSGPRs', '?')} | {r.get('ScratchSize [bytes/lane]', '?')} | "
+                     f"{r.get('LDS Size [bytes/block]', '?')} | "
+                     f"{r.get('Occupancy [waves/SIMD]', '?')} |")
+    with open(out_path, "w") as fh:
+        fh.write("# Kernel resources (compiler resource-usage remarks, gfx950)\n\n"
+                 "Command: `python paper_2606_15437_amd/build.py --resources "
+                 "profiles/kernel_resources.md` (device-only compile of every HIP source with "
+                 "`-Rpass-analysis=kernel-resource-usage` and the library's flags).\n\n")
+        fh.write("\n".join(lines) + "\n")
+    return out_path
+
+
 if __name__ == "__main__":
     import sys
-    print(build(verbose=True, force="--changed" not in sys.argv))
+    if "--resources" in sys.argv:
+        print(resources(sys.argv[sys.argv.index("--resources") + 1]))
+    else:
+        print(build(verbose=True, force="--changed" not in sys.argv))

@@ -38,23 +38,29 @@ __global__ __launch_bounds__(256) void calib_int32(uint32_t* out, uint32_t iters
 hipError_t run_calibration(int cus, uint32_t iters, double* lane_ops_per_s, hipStream_t s) {
   const int blocks = cus * 32;  // 8 waves per SIMD
   uint32_t* out = nullptr;
-  hipEvent_t e0, e1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipMalloc(&out, sizeof(uint32_t) * blocks * 256);
-  if (e != hipSuccess) return e;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
-  hipLaunchKernelGGL(calib_int32, dim3(blocks), dim3(256), 0, s, out, iters / 8, 1u);
-  hipEventRecord(e0, s);
-  hipLaunchKernelGGL(calib_int32, dim3(blocks), dim3(256), 0, s, out, iters, 2u);
-  hipEventRecord(e1, s);
-  e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(calib_int32, dim3(blocks), dim3(256), 0, s, out, iters / 8, 1u);  // warm
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(calib_int32, dim3(blocks), dim3(256), 0, s, out, iters, 2u);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0.f;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
   if (e == hipSuccess)
     *lane_ops_per_s = 12.0 * iters * (double)blocks * 256.0 / (ms * 1e-3);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  hipFree(out);
+  // release what was created; the first failure is the one reported
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (out) (void)hipFree(out);
   return e;
 }
 
