@@ -22,6 +22,8 @@ Also reported in the JSON line:
   - table1: the paper's matched single-formula workload;
   - split: the split search (Definition 2, Proposition 5) of formula pairs that agree on
     every model with at most 4 worlds, over the 6-, 7- and 8-world frame families;
+  - mlp_scoring: the pair MLP's forward throughput on 2^20 pairs against the BF16
+    matrix-core peak;
   - learned: the learned pair proposal at full scale (10,000-formula corpus, ~5.5M-pair
     universe, 10^6 budget), every proposal verified exactly, against plain enumeration;
   - census_reproduction: the paper's five-world census (Section 6): 44,678 enumerated
@@ -179,6 +181,38 @@ def bench_cpu(fs, reps=5):
                               "hardware": "Xeon Platinum 8480+ and H100 PCIe"}}
 
 
+PEAK_BF16 = 2.5e15  # dense BF16 matrix-core peak of one MI355X (FLOP/s)
+
+
+def bench_mlp(stream, npairs=1 << 20, reps=3):
+    """Scoring throughput of the pair MLP (8192 -> 512 -> 256 -> 1, BF16 operands, FP32
+    accumulation) on seeded random signatures, in the scoring path's chunks."""
+    import statistics
+    import torch
+    from paper_2606_15437_amd import kripke as K
+    from paper_2606_15437_amd.proposal import SCORE_CHUNK
+    rng = np.random.default_rng(0x5C0)
+    sig = rng.integers(0, 2 ** 63, size=(10000, 64), dtype=np.uint64)
+    ij = rng.integers(0, 10000, size=(npairs, 2)).astype(np.uint64)
+    pairs = (ij[:, 0] << np.uint64(32)) | ij[:, 1]
+    d_sig = torch.as_tensor(sig.view(np.int64), device="cuda")
+    d_pairs = torch.as_tensor(pairs.view(np.int64), device="cuda")
+    d_z = torch.empty(npairs, dtype=torch.float32, device="cuda")
+    h = K.kripke_mlp_create(1, SCORE_CHUNK)
+    try:
+        K.kripke_mlp_forward(h, d_sig, d_pairs, d_z, stream)
+        ms = statistics.median(timed(lambda: K.kripke_mlp_forward(h, d_sig, d_pairs, d_z, stream),
+                                     stream) for _ in range(reps))
+    finally:
+        K.kripke_mlp_destroy(h)
+    flop = 2.0 * npairs * (8192 * 512 + 512 * 256 + 256)
+    log(f"mlp forward: {npairs} pairs in {ms:.1f} ms, {flop / ms / 1e9:.1f} TFLOP/s")
+    return {"pairs": npairs, "chunk": SCORE_CHUNK, "ms": ms, "TFLOP_per_s": flop / ms / 1e9,
+            "roofline": {"bound": "mfma", "achieved": flop / ms / 1e9, "peak": PEAK_BF16 / 1e12,
+                         "unit": "TFLOP/s", "frac": flop / ms / 1e-3 / PEAK_BF16},
+            "flop_per_pair": flop / npairs}
+
+
 def bench_learned():
     """The learned proposal protocol at full scale (every heavy step in the library)."""
     from paper_2606_15437_amd import proposal as P
@@ -282,6 +316,8 @@ def main():
     ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-reproduction", action="store_true")
+    ap.add_argument("--only", choices=("mlp", "split"),
+                    help="run one secondary leg alone and print its record (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -292,6 +328,13 @@ def main():
     import torch
     from paper_2606_15437_amd import inputs as I
     from paper_2606_15437_amd import kripke as K
+
+    if args.only:
+        torch.cuda.set_device(0)
+        stream = torch.cuda.current_stream()
+        leg = bench_mlp(stream) if args.only == "mlp" else bench_split(args, stream)
+        print(json.dumps({"only": args.only, args.only: leg}))
+        return
 
     n, nvars = 5, 2
     nval = 1 << (n * nvars)
@@ -384,6 +427,7 @@ def main():
     cpu = None if args.no_cpu else bench_cpu(fs)
 
     split = None if args.no_split else bench_split(args, stream)
+    mlp = bench_mlp(stream)
     learned = None if args.no_learned else bench_learned()
     reproduction = None if args.no_reproduction else bench_reproduction()
     synthesis = bench_synthesis()
@@ -426,6 +470,7 @@ def main():
         "plain_vs_batched": plain,
         "table1": table1,
         "split": split,
+        "mlp_scoring": mlp,
         "learned": learned,
         "census_reproduction": reproduction,
         "active_synthesis": synthesis,

@@ -200,6 +200,12 @@ class Verifier:
         return hit, {"agree4": agree, "keys": keys, "n": where}
 
 
+# Pairs per forward chunk when scoring a universe: large enough that the first
+# layer's GEMM runs with its widest per-wave tiles (they need a grid of at least 1,024
+# blocks of 128 x 256 outputs, i.e. 65,536 or more pairs per chunk).
+SCORE_CHUNK = 1 << 18
+
+
 def train_mlp(d_sig, d_pairs, labels, steps=400, batch=512, lr=1e-3, seed=17, log=None):
     """Train the scorer on labelled pairs (balanced sampling is left to pos_weight)."""
     torch = _t()
@@ -207,7 +213,7 @@ def train_mlp(d_sig, d_pairs, labels, steps=400, batch=512, lr=1e-3, seed=17, lo
     pos = float(labels.sum())
     pos_weight = float((n - pos) / max(pos, 1.0))
     d_y_all = torch.as_tensor(labels.astype(np.float32), device="cuda")
-    h = K.kripke_mlp_create(seed, max(batch, 16384))
+    h = K.kripke_mlp_create(seed, max(batch, SCORE_CHUNK))
     d_loss = torch.zeros(1, dtype=torch.float32, device="cuda")
     rng = np.random.default_rng(seed)
     losses = []

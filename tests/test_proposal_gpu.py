@@ -141,6 +141,43 @@ def test_mlp_forward_matches_reference(kr):
         kr.kripke_mlp_destroy(h)
 
 
+def test_mlp_wide_tiles_match_narrow_and_reference(kr):
+    """A forward of 65,536 pairs in one chunk runs the first layer with 2 x 4 MFMA tiles
+    per wave (the scoring path's chunks); it equals, bit for bit, the same pairs forwarded
+    in chunks of 512 (one tile per wave), and sampled rows match the CPU reference."""
+    import torch
+    from oracle import mlp_ref as R
+    rng = np.random.default_rng(21)
+    sig = rng.integers(0, 2 ** 63, size=(300, 64), dtype=np.uint64)
+    M = 65536
+    ij = rng.integers(0, 300, size=(M, 2))
+    pairs = (ij[:, 0].astype(np.uint64) << np.uint64(32)) | ij[:, 1].astype(np.uint64)
+    d_sig = torch.as_tensor(sig.view(np.int64), device="cuda")
+    d_pairs = torch.as_tensor(pairs.view(np.int64), device="cuda")
+    wide = kr.kripke_mlp_create(31, M)
+    narrow = kr.kripke_mlp_create(31, 512)
+    try:
+        p = kr.kripke_mlp_get_params(wide)
+        named = kr.split_params(p)
+        for b in ("b1", "b2", "b3"):
+            named[b][:] = rng.normal(0, 0.05, named[b].shape)
+        kr.kripke_mlp_set_params(wide, p)
+        kr.kripke_mlp_set_params(narrow, p)
+        z_w = torch.zeros(M, dtype=torch.float32, device="cuda")
+        z_n = torch.zeros(M, dtype=torch.float32, device="cuda")
+        kr.kripke_mlp_forward(wide, d_sig, d_pairs, z_w)
+        kr.kripke_mlp_forward(narrow, d_sig, d_pairs, z_n)
+        torch.cuda.synchronize()
+        zw, zn = z_w.cpu().numpy(), z_n.cpu().numpy()
+        assert (zw.view(np.uint32) == zn.view(np.uint32)).all()
+        rows = rng.choice(M, 96, replace=False)
+        ref = R.forward(R.unflatten(p), R.pair_inputs(sig, pairs[rows]))["z"]
+        assert _close(zw[rows], ref, 1e-2)
+    finally:
+        kr.kripke_mlp_destroy(wide)
+        kr.kripke_mlp_destroy(narrow)
+
+
 def test_mlp_gradients_and_adam_match_reference(kr):
     import torch
     from oracle import mlp_ref as R
