@@ -809,10 +809,11 @@ static std::string tune_key(const KripkePlan* p) {
   for (uint8_t b : p->mb.code) h = (h ^ b) * 1099511628211ull;
   hipDeviceProp_t prop;
   int dev = 0;
-  hipGetDevice(&dev);
-  hipGetDeviceProperties(&prop, dev);
+  char arch[sizeof prop.gcnArchName] = "unknown-device";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
   char buf[256];
-  snprintf(buf, sizeof buf, "%s/%dcu/n%d/v%d/m%u/B%u/h%016llx%s", prop.gcnArchName, p->ds->cus,
+  snprintf(buf, sizeof buf, "%s/%dcu/n%d/v%d/m%u/B%u/h%016llx%s", arch, p->ds->cus,
            p->n, p->nvars, p->class_mask, p->nformulas, (unsigned long long)h,
            p->plain ? "/per-formula" : "");
   for (char* c = buf; *c; ++c)
@@ -879,11 +880,21 @@ static int tune_plan(KripkePlan* p, const char* path) {
     p->tiers = t;
     return upload_order(t, p->db.order, p->cap);
   }
-  kripke_census_result* trial_out = nullptr;
-  KR_HIP(hipMalloc(&trial_out, sizeof(kripke_census_result) * 4 * p->nformulas));
-  hipEvent_t e0, e1;
-  KR_HIP(hipEventCreate(&e0));
-  KR_HIP(hipEventCreate(&e1));
+  // trial outputs and timing events, released on every return path
+  struct Trial {
+    kripke_census_result* out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Trial() {
+      if (out) (void)hipFree(out);
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } trial;
+  KR_HIP(hipMalloc(&trial.out, sizeof(kripke_census_result) * 4 * p->nformulas));
+  KR_HIP(hipEventCreate(&trial.e0));
+  KR_HIP(hipEventCreate(&trial.e1));
+  kripke_census_result* trial_out = trial.out;
+  hipEvent_t e0 = trial.e0, e1 = trial.e1;
   const uint64_t slice = std::min<uint64_t>(1ull << (p->n * p->n), 1ull << 20);
   double best = 1e300;
   int best_ls = p->ls, best_ipw = p->ipw;
@@ -909,9 +920,6 @@ static int tune_plan(KripkePlan* p, const char* path) {
       if (first_res.empty()) {
         first_res = res;
       } else if (memcmp(first_res.data(), res.data(), res.size() * sizeof(res[0])) != 0) {
-        hipFree(trial_out);
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
         return fail(KRIPKE_EINTERNAL, "autotuner: tile candidate ls=" + std::to_string(l) +
                                           " ipw=" + std::to_string(w) +
                                           " disagrees with the first candidate");
@@ -927,9 +935,6 @@ static int tune_plan(KripkePlan* p, const char* path) {
   p->ipw = best_ipw;
   make_tiers(p->mb, p->n, p->nvars, 0, true, best_ls, &p->tiers);
   if (int rc1 = upload_order(p->tiers, p->db.order, p->cap)) return rc1;
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  KR_HIP(hipFree(trial_out));
   tune_store(path, key, best_ls, best_ipw, best);
   return KRIPKE_OK;
 }
@@ -1101,7 +1106,7 @@ int kripke_mlp_destroy(void* mlp) {
                   S->a2b, S->a2, S->logit, S->dz, S->lossv, S->dh2f, S->dh1f, S->dh2, S->dh2t,
                   S->dh1t};
   for (void* q : ptrs)
-    if (q) hipFree(q);
+    if (q) (void)hipFree(q);
   delete S;
   return KRIPKE_OK;
 }
@@ -1230,7 +1235,7 @@ int kripke_plan_create(const uint8_t* code, const uint32_t* offsets, uint32_t nf
   }
   if ((rc = upload(p->mb, &p->db, 4, p->cap)) ||
       (p->ls >= 0 && (rc = upload_order(p->tiers, p->db.order, p->cap)))) {
-    hipStreamDestroy(p->cap);
+    (void)hipStreamDestroy(p->cap);
     delete p;
     return rc;
   }
@@ -1304,12 +1309,12 @@ int kripke_plan_destroy(void* plan) {
   g_err.clear();
   auto* p = static_cast<KripkePlan*>(plan);
   if (!p) return KRIPKE_OK;
-  if (p->exec) hipGraphExecDestroy(p->exec);
-  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap) {
     release(&p->db, p->cap);
-    hipStreamSynchronize(p->cap);
-    hipStreamDestroy(p->cap);
+    (void)hipStreamSynchronize(p->cap);
+    (void)hipStreamDestroy(p->cap);
   }
   delete p;
   return KRIPKE_OK;

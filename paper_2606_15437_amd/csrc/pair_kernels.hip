@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void knn_kernel(const uint64_t* sig, uint32_t 
   __shared__ uint32_t hist[kMaxBits + 1];
   __shared__ uint64_t row[kMaxBits / 64];
   __shared__ uint32_t wave_cnt[4][2];
-  __shared__ uint32_t thresh, need_eq, run_lt, run_eq, run_out;
+  __shared__ uint32_t thresh, need_eq, run_eq, run_out;
   const uint32_t i = blockIdx.x;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   for (uint32_t w = t; w < words; w += 256) row[w] = sig[(uint64_t)i * words + w];
@@ -133,22 +133,34 @@ int knn_pairs_canonical(const uint32_t* nbr, uint32_t nformulas, uint32_t k, uin
   uint64_t *keys = nullptr, *sorted = nullptr;
   void* tmp = nullptr;
   size_t tmp_sort = 0, tmp_uniq = 0;
-  if (hipMallocAsync((void**)&keys, n * 8, s) != hipSuccess) return -5;
-  if (hipMallocAsync((void**)&sorted, n * 8, s) != hipSuccess) return -5;
-  hipLaunchKernelGGL(pair_keys, dim3(blocks_for(n)), dim3(256), 0, s, nbr, nformulas, k, keys);
-  hipcub::DeviceRadixSort::SortKeys(nullptr, tmp_sort, keys, sorted, (int)n, 0, 64, s);
-  hipcub::DeviceSelect::Unique(nullptr, tmp_uniq, sorted, pairs, npairs, (int)n, s);
-  const size_t tb = tmp_sort > tmp_uniq ? tmp_sort : tmp_uniq;
-  if (hipMallocAsync(&tmp, tb, s) != hipSuccess) return -5;
-  size_t b1 = tb, b2 = tb;
-  if (hipcub::DeviceRadixSort::SortKeys(tmp, b1, keys, sorted, (int)n, 0, 64, s) != hipSuccess)
-    return -4;
-  if (hipcub::DeviceSelect::Unique(tmp, b2, sorted, pairs, npairs, (int)n, s) != hipSuccess)
-    return -4;
-  hipFreeAsync(tmp, s);
-  hipFreeAsync(keys, s);
-  hipFreeAsync(sorted, s);
-  return 0;
+  int rc = 0;  // 0, -5 (allocation failed) or -4 (a HIP or hipCUB call failed)
+  if (hipMallocAsync((void**)&keys, n * 8, s) != hipSuccess ||
+      hipMallocAsync((void**)&sorted, n * 8, s) != hipSuccess) {
+    rc = -5;
+  } else {
+    hipLaunchKernelGGL(pair_keys, dim3(blocks_for(n)), dim3(256), 0, s, nbr, nformulas, k, keys);
+    if (hipGetLastError() != hipSuccess ||
+        hipcub::DeviceRadixSort::SortKeys(nullptr, tmp_sort, keys, sorted, (int)n, 0, 64, s) !=
+            hipSuccess ||
+        hipcub::DeviceSelect::Unique(nullptr, tmp_uniq, sorted, pairs, npairs, (int)n, s) !=
+            hipSuccess)
+      rc = -4;
+  }
+  if (rc == 0) {
+    const size_t tb = tmp_sort > tmp_uniq ? tmp_sort : tmp_uniq;
+    size_t b1 = tb, b2 = tb;
+    if (hipMallocAsync(&tmp, tb, s) != hipSuccess)
+      rc = -5;
+    else if (hipcub::DeviceRadixSort::SortKeys(tmp, b1, keys, sorted, (int)n, 0, 64, s) !=
+                 hipSuccess ||
+             hipcub::DeviceSelect::Unique(tmp, b2, sorted, pairs, npairs, (int)n, s) != hipSuccess)
+      rc = -4;
+  }
+  // stream-ordered frees after the work that uses the buffers
+  if (tmp) (void)hipFreeAsync(tmp, s);
+  if (keys) (void)hipFreeAsync(keys, s);
+  if (sorted) (void)hipFreeAsync(sorted, s);
+  return rc;
 }
 
 hipError_t launch_pair_hamming(const uint64_t* sig, uint32_t words, const uint64_t* pairs,
@@ -166,27 +178,36 @@ int select_top(const float* scores, uint64_t n, uint64_t budget, uint64_t* idx, 
   uint64_t *vals = nullptr, *vals_out = nullptr;
   void* tmp = nullptr;
   size_t tb = 0;
-  if (hipMallocAsync((void**)&keys, n * 4, s) != hipSuccess) return -5;
-  if (hipMallocAsync((void**)&keys_out, n * 4, s) != hipSuccess) return -5;
-  if (hipMallocAsync((void**)&vals, n * 8, s) != hipSuccess) return -5;
-  if (hipMallocAsync((void**)&vals_out, n * 8, s) != hipSuccess) return -5;
-  hipLaunchKernelGGL(score_keys, dim3(blocks_for(n)), dim3(256), 0, s, scores, n, keys);
-  hipLaunchKernelGGL(iota_u64, dim3(blocks_for(n)), dim3(256), 0, s, vals, n);
-  hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tb, keys, keys_out, vals, vals_out, (int)n,
-                                               0, 32, s);
-  if (hipMallocAsync(&tmp, tb, s) != hipSuccess) return -5;
-  if (hipcub::DeviceRadixSort::SortPairsDescending(tmp, tb, keys, keys_out, vals, vals_out,
-                                                   (int)n, 0, 32, s) != hipSuccess)
-    return -4;
-  if (hipMemcpyAsync(idx, vals_out, (budget < n ? budget : n) * 8, hipMemcpyDeviceToDevice, s) !=
-      hipSuccess)
-    return -4;
-  hipFreeAsync(tmp, s);
-  hipFreeAsync(keys, s);
-  hipFreeAsync(keys_out, s);
-  hipFreeAsync(vals, s);
-  hipFreeAsync(vals_out, s);
-  return 0;
+  int rc = 0;  // 0, -5 (allocation failed) or -4 (a HIP or hipCUB call failed)
+  if (hipMallocAsync((void**)&keys, n * 4, s) != hipSuccess ||
+      hipMallocAsync((void**)&keys_out, n * 4, s) != hipSuccess ||
+      hipMallocAsync((void**)&vals, n * 8, s) != hipSuccess ||
+      hipMallocAsync((void**)&vals_out, n * 8, s) != hipSuccess) {
+    rc = -5;
+  } else {
+    hipLaunchKernelGGL(score_keys, dim3(blocks_for(n)), dim3(256), 0, s, scores, n, keys);
+    hipLaunchKernelGGL(iota_u64, dim3(blocks_for(n)), dim3(256), 0, s, vals, n);
+    if (hipGetLastError() != hipSuccess ||
+        hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tb, keys, keys_out, vals, vals_out,
+                                                     (int)n, 0, 32, s) != hipSuccess)
+      rc = -4;
+  }
+  if (rc == 0) {
+    if (hipMallocAsync(&tmp, tb, s) != hipSuccess)
+      rc = -5;
+    else if (hipcub::DeviceRadixSort::SortPairsDescending(tmp, tb, keys, keys_out, vals, vals_out,
+                                                          (int)n, 0, 32, s) != hipSuccess ||
+             hipMemcpyAsync(idx, vals_out, (budget < n ? budget : n) * 8,
+                            hipMemcpyDeviceToDevice, s) != hipSuccess)
+      rc = -4;
+  }
+  // stream-ordered frees after the work that uses the buffers
+  if (tmp) (void)hipFreeAsync(tmp, s);
+  if (keys) (void)hipFreeAsync(keys, s);
+  if (keys_out) (void)hipFreeAsync(keys_out, s);
+  if (vals) (void)hipFreeAsync(vals, s);
+  if (vals_out) (void)hipFreeAsync(vals_out, s);
+  return rc;
 }
 
 }  // namespace kripke
