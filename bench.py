@@ -98,6 +98,7 @@ def bench_split(args, stream):
     st = K.kripke_program_stats(*I.pack([I.iff(a, b) for a, b in pairs]), 2)
     per = {}
     tot_ms = tot_evals = tot_ops = 0.0
+    separated = np.zeros(len(pairs), dtype=bool)
     for n in (6, 7, 8):
         frames = I.frame_family(n, args.split_frames)
         d_fr = torch.as_tensor(np.ascontiguousarray(frames).view(np.int32), device="cuda")
@@ -108,6 +109,7 @@ def bench_split(args, stream):
         keys = K.as_u64(out)
         nval = 1 << (2 * n)
         found = keys != K.NO_KEY
+        separated |= found
         # frames actually scanned: up to the separating one, else all of them
         scanned = np.where(found, (keys >> np.uint64(2 * n + 4)).astype(np.float64) + 1,
                            float(len(frames)))
@@ -133,7 +135,8 @@ def bench_split(args, stream):
                          "kernel": "census_fast<8,2,*,LIST>",
                          "all_n_achieved": tot_ops / tot_ms / 1e9},
             "selection": dict(stats, seconds=sel_s),
-            "note": "timed per call including host compile and upload of the pair programs"}
+            "note": "timed per call including host compile and upload of the pair programs",
+            "_survivors": (pairs, separated)}
 
 
 def bench_cpu(fs, reps=5):
@@ -285,9 +288,16 @@ def bench_correspondence():
     return out
 
 
-def bench_adversarial():
+def bench_adversarial(split_survivors=None):
     from paper_2606_15437_amd import adversarial as A
+    c4 = None
+    if split_survivors is not None:
+        c4, _ = A.run_c4(*split_survivors, log=log)
     rec, _ = A.run(frames_per=16384, log=log)
+    rec["input"] = ("the context-iteration mining candidates of Section 7 (the paper's "
+                    "adversarial input came from its mining report); c4_survivors: the same "
+                    "generators on pairs of the pair-separation workload no family frame split")
+    rec["c4_survivors"] = c4
     rec["relations"] = sum(g["relations"] for g in rec["adversarial"].values())
     rec["valuation_frame_evals"] = sum(g["valuation_frame_evals"]
                                        for g in rec["adversarial"].values())
@@ -333,6 +343,7 @@ def main():
         torch.cuda.set_device(0)
         stream = torch.cuda.current_stream()
         leg = bench_mlp(stream) if args.only == "mlp" else bench_split(args, stream)
+        leg.pop("_survivors", None)
         print(json.dumps({"only": args.only, args.only: leg}))
         return
 
@@ -432,7 +443,8 @@ def main():
     reproduction = None if args.no_reproduction else bench_reproduction()
     synthesis = bench_synthesis()
     correspondence = None if args.no_reproduction else bench_correspondence()
-    adversarial = None if args.no_reproduction else bench_adversarial()
+    survivors = split.pop("_survivors") if split else None
+    adversarial = None if args.no_reproduction else bench_adversarial(survivors)
 
     valid = {name: int((res[c, :, 0] == K.NO_KEY).sum()) for c, name in enumerate("K T S4 S5".split())}
     rec = {

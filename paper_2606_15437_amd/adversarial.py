@@ -10,8 +10,10 @@ worlds.
 Adversarial synthesis: the exact-prefix survivors are then split on frames from six
 generators (Erdos-Renyi, edge-flip mutation of canonical seeds, SCC bottlenecks,
 dead-end insertion, back-edge injection, permuted bottlenecks) at n = 6, 8, ..., 16;
-one-variable pairs only through twelve worlds, constant pairs at every size.  Every
-evaluation runs in the library's kernels.
+one-variable pairs only through twelve worlds, constant pairs at every size.  The same
+generators also run on survivors of the pair-separation workload (two-variable pairs
+that agree through four worlds and that no family frame separated), at 6 and 8 worlds.
+Every evaluation runs in the library's kernels.
 """
 from __future__ import annotations
 
@@ -123,9 +125,11 @@ def template_stress(cands, sizes=range(6, 17)):
     return sep, wit
 
 
-def adversarial(cands, frames_per=4096, sizes=SIZES, one_var_max=12, log=None):
+def adversarial(cands, frames_per=4096, sizes=SIZES, one_var_max=12, two_var_max=8, log=None):
     """Split every candidate on every generator's frames; per generator: relations,
-    pair-frame tests, valuation-frame evaluations, verified separations and seconds."""
+    pair-frame tests, valuation-frame evaluations, verified separations and seconds.
+    One-variable pairs run through one_var_max worlds and two-variable pairs through
+    two_var_max (4^n valuations per frame), constant pairs at every size."""
     import torch
     stats = {}
     hits = {}
@@ -135,8 +139,8 @@ def adversarial(cands, frames_per=4096, sizes=SIZES, one_var_max=12, log=None):
         found = set()
         for n in sizes:
             frames = I.adversarial_frames(g, n, frames_per)
-            for nv in (0, 1):
-                if nv == 1 and n > one_var_max:
+            for nv in sorted({c[3] for c in cands}):
+                if (nv == 1 and n > one_var_max) or (nv >= 2 and n > two_var_max):
                     continue
                 idx = [i for i, c in enumerate(cands) if c[3] == nv]
                 if not idx:
@@ -163,6 +167,28 @@ def adversarial(cands, frames_per=4096, sizes=SIZES, one_var_max=12, log=None):
         if log:
             log(f"adversarial {g}: {rel} relations, {len(found)} pairs separated, {t_gpu:.2f} s")
     return stats, hits
+
+
+def c4_survivors(pairs, separated, sample=1024, seed=I.SEED_ADV):
+    """The adversarial input of the pair-separation workload: a seeded sample of its pairs
+    (two variables, agreeing on every model with at most four worlds) that no frame of the
+    6-, 7- and 8-world families separated; as [(label, phi, psi, 2)]."""
+    idx = [i for i in range(len(pairs)) if not separated[i]]
+    rng = I.SplitMix64(seed, 11)
+    pick = sorted(set(idx[rng.below(len(idx))] for _ in range(4 * sample)))[:sample] \
+        if len(idx) > sample else idx
+    return [(("c4", i), pairs[i][0], pairs[i][1], 2) for i in pick]
+
+
+def run_c4(pairs, separated, sample=1024, frames_per=1024, log=print):
+    """Adversarial frames (six generators, n = 6 and 8) on C4 survivors."""
+    t0 = time.time()
+    cands = c4_survivors(pairs, separated, sample)
+    stats, hits = adversarial(cands, frames_per, sizes=(6, 8), log=log)
+    return {"survivors_total": int(sum(1 for x in separated if not x)),
+            "sampled": len(cands), "frames_per_generator_and_n": frames_per, "sizes": [6, 8],
+            "adversarial": stats, "adversarial_separated": len(hits),
+            "seconds": time.time() - t0}, hits
 
 
 def run(frames_per=4096, log=print):

@@ -305,8 +305,18 @@ def run(n_test=10000, n_train=10000, universe_pairs=5_500_000, train_pairs=5_500
         hits = int(hit.sum())
         # every ranking is stable, so a smaller budget's selection is a prefix
         prefix = {str(b): int(hit[:b].sum()) for b in (10_000, 100_000) if b < len(ids)}
+        # the smallest budget at which this ranking holds a given share of every late
+        # split verified in the union of the rankings (None if it never does)
+        total = int(hit_u.sum())
+        cum = np.cumsum(hit)
+        reach = {}
+        for share in (0.5, 0.9):
+            need = int(np.ceil(share * total))
+            at = int(np.searchsorted(cum, need)) if need else 0
+            reach[str(share)] = at + 1 if total and at < len(cum) else None
         rec[name] = {"evaluated": int(len(ids)), "hits": hits,
-                     "hits_per_1e6": hits * 1e6 / max(len(ids), 1), "hits_at_budget": prefix}
+                     "hits_per_1e6": hits * 1e6 / max(len(ids), 1), "hits_at_budget": prefix,
+                     "budget_for_share_of_all_hits": reach}
         log(f"{name}: {hits} verified late splits in {len(ids)} pairs; at smaller budgets "
             f"{prefix}")
     rec["test"]["verify_stages_s"] = dict(ver.stage_s)
