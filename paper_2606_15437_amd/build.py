@@ -92,13 +92,32 @@ def resources(out_path: str, sources=None) -> str:
                            capture_output=True, text=True).stdout.splitlines()
     lines = ["| source | kernel | VGPRs | AGPRs | SGPRs | scratch B/lane | LDS B/block | "
              "waves/SIMD |", "|---|---|---|---|---|---|---|---|"]
+    # library (rocPRIM/hipCUB) instantiations: one summary row per source, not one per
+    # template instance
+    lib = {}
     for r, nm in zip(rows, names):
+        if "rocprim::" in nm or "hipcub::" in nm:
+            d = lib.setdefault(r["src"], {"count": 0, "vgpr": 0, "sgpr": 0, "scratch": 0})
+            d["count"] += 1
+            for key, field in (("vgpr", "VGPRs"), ("sgpr", "TotalSGPRs"),
+                               ("scratch", "ScratchSize [bytes/lane]")):
+                try:
+                    d[key] = max(d[key], int(r.get(field, 0)))
+                except ValueError:
+                    pass
+    for r, nm in zip(rows, names):
+        if "rocprim::" in nm or "hipcub::" in nm:
+            continue
         nm = nm.replace("kripke::", "").replace("(anonymous namespace)::", "")
         nm = nm.replace("|", "\\|")
         lines.append(f"| {r['src']} | `{nm}` | {r.get('VGPRs', '?')} | {r.get('AGPRs', '?')} | "
                      f"{r.get('TotalSGPRs', '?')} | {r.get('ScratchSize [bytes/lane]', '?')} | "
                      f"{r.get('LDS Size [bytes/block]', '?')} | "
                      f"{r.get('Occupancy [waves/SIMD]', '?')} |")
+    for src, d in sorted(lib.items()):
+        lines.append(f"| {src} | {d['count']} rocPRIM/hipCUB sort and scan instantiations "
+                     f"(maxima over them) | {d['vgpr']} | — | {d['sgpr']} | {d['scratch']} | "
+                     f"— | — |")
     with open(out_path, "w") as fh:
         fh.write("# Kernel resources (compiler resource-usage remarks, gfx950)\n\n"
                  "Command: `python paper_2606_15437_amd/build.py --resources "
