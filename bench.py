@@ -92,7 +92,8 @@ def bench_split(args, stream):
     from paper_2606_15437_amd import kripke as K
     from paper_2606_15437_amd.split_workload import config4_pairs
     t0 = time.time()
-    pairs, stats = config4_pairs(args.split_pairs, pool=args.split_pool)
+    log(f"split: selecting {args.split_pairs} pairs from a pool of {args.split_pool} formulas")
+    pairs, stats = config4_pairs(args.split_pairs, pool=args.split_pool, log=log)
     sel_s = time.time() - t0
     code, offs = I.pack([p for ab in pairs for p in ab])
     st = K.kripke_program_stats(*I.pack([I.iff(a, b) for a, b in pairs]), 2)
@@ -104,7 +105,9 @@ def bench_split(args, stream):
         d_fr = torch.as_tensor(np.ascontiguousarray(frames).view(np.int32), device="cuda")
         out = torch.empty(len(pairs), dtype=torch.int64, device="cuda")
         run = lambda: K.kripke_split_batch(code, offs, d_fr, n, 2, out, stream)
-        run()
+        # warm-up on the first frames only (loads the kernels; the full scan is long)
+        K.kripke_split_batch(code, offs, d_fr[:4096], n, 2, out, stream)
+        log(f"split n={n}: scanning {len(pairs)} pairs x {len(frames)} frames")
         ms = timed(run, stream)
         keys = K.as_u64(out)
         nval = 1 << (2 * n)
@@ -335,6 +338,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    # the library's autotuner reports each candidate it times (stderr)
+    os.environ.setdefault("KRIPKE_TUNE_LOG", "1")
     import torch
     from paper_2606_15437_amd import inputs as I
     from paper_2606_15437_amd import kripke as K
@@ -403,6 +408,8 @@ def main():
         for name, mask, cache in (("plain", 0xF | K.KRIPKE_PLAN_PLAIN, None),
                                   ("per_formula_autotuned", 0xF | K.KRIPKE_PLAN_PLAIN,
                                    args.tune_cache)):
+            log(f"{name}: creating the per-formula plan"
+                + (" (autotuned unless cached)" if cache else ""))
             t0 = time.time()
             pplan = K.kripke_plan_create(code, offs, n, mask, nvars, tune_cache=cache)
             create_s = time.time() - t0

@@ -165,7 +165,9 @@ void kripke_frame_decode(uint64_t frame, uint32_t n, uint32_t *succ /* [n] */);
  * (frame sets per lane, work items per wave).  NULL uses the defaults; with
  * a path, a cached choice for this device, n, nvars and batch is reused, and
  * otherwise every candidate is timed on a slice of the frames at creation
- * and the winner is appended to the file.
+ * (the per-formula form below: on the first 256 formulas of the batch)
+ * and the winner is appended to the file.  With the environment variable
+ * KRIPKE_TUNE_LOG=1 each candidate's time is printed to stderr.
  * d_out: device array [4][nformulas] (class-major); rows of classes not in
  * class_mask are left untouched.
  * Every tile candidate the autotuner times must give identical results on

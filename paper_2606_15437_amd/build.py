@@ -21,12 +21,13 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",
 
 
 def _stale(src: str, obj: str) -> bool:
-    """An object is stale if it is older than its source or any header in csrc."""
+    """An object is stale if it is older than its source or any header in csrc or include."""
     if not os.path.exists(obj):
         return True
     t = os.path.getmtime(obj)
-    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, h) for h in os.listdir(CSRC)
-                                        if h.endswith(".h")]
+    inc = os.path.join(os.path.dirname(HERE), "include")
+    deps = [os.path.join(CSRC, src)] + [os.path.join(d, h) for d in (CSRC, inc)
+                                        for h in os.listdir(d) if h.endswith(".h")]
     return any(os.path.getmtime(d) > t for d in deps)
 
 

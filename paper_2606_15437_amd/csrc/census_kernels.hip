@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 
 #include "kripke_internal.h"
@@ -498,13 +499,19 @@ static hipError_t launch_one(const CensusArgs& a, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Resident blocks per CU, queried once per kernel (the query costs about a
+// millisecond of host time, which per-formula launch loops would pay each time).
 template <int N, int NV>
 static int occupancy_one() {
-  int blocks = 0;
+  static std::atomic<int> cached{0};
+  int blocks = cached.load(std::memory_order_relaxed);
+  if (blocks > 0) return blocks;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, census_generic<N, NV>, 256, 0) !=
-      hipSuccess)
+          hipSuccess ||
+      blocks <= 0)
     return 1;
-  return blocks > 0 ? blocks : 1;
+  cached.store(blocks, std::memory_order_relaxed);
+  return blocks;
 }
 
 #define KR_NV_TABLE(N) {&launch_one<N, 0>, &launch_one<N, 1>, &launch_one<N, 2>, \

@@ -29,6 +29,7 @@
 // 11 .. 11+LS-1 (between the lane bits and the chunk loop) instead of frames.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 
 #include "census_kernels.h"
@@ -826,13 +827,19 @@ hipError_t launch_t(const FastArgs& a, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Resident blocks per CU, queried once per variant (the query costs about a
+// millisecond of host time, which per-formula launch loops would pay each time).
 template <int N, int NV, int LS, int MODE, bool FUSED>
 int occ_t() {
-  int b = 0;
+  static std::atomic<int> cached{0};
+  int b = cached.load(std::memory_order_relaxed);
+  if (b > 0) return b;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, census_fast<N, NV, LS, MODE, FUSED>, 256,
-                                                   0) != hipSuccess)
+                                                   0) != hipSuccess ||
+      b <= 0)
     return 1;
-  return b > 0 ? b : 1;
+  cached.store(b, std::memory_order_relaxed);
+  return b;
 }
 
 struct Entry {

@@ -741,6 +741,7 @@ struct KripkePlan {
 
 static int plan_enqueue(KripkePlan* p, kripke_census_result* d_out, hipStream_t s,
                         uint64_t frames);
+static void plan_free(KripkePlan* p);
 
 // The unbatched baselines, one launch (pair) per formula, each restricted to
 // that formula through a one-entry slice of the order array:
@@ -750,13 +751,16 @@ static int plan_enqueue(KripkePlan* p, kripke_census_result* d_out, hipStream_t 
 //     the tuned tiles, one launch per formula, over frames [0, frames) (0 =
 //     all), so only batching separates it from the batched plan.
 static int plan_enqueue_plain(KripkePlan* p, kripke_census_result* d_out, hipStream_t s,
-                              uint64_t frames = 0) {
+                              uint64_t frames = 0, uint32_t count = 0) {
   if (p->ls >= 0) {
+    // count: launch only formulas 0 .. count-1 of the batch (0 = all); the autotuner
+    // times candidates on such a subset, the same one whatever the candidate's tiers
     const uint64_t nf = frames ? frames : 1ull << (p->n * p->n);
     auto* key = reinterpret_cast<unsigned long long*>(&d_out[0].first_key);
     auto* cnt = reinterpret_cast<unsigned long long*>(&d_out[0].fail_count);
     KR_HIP(launch_init(key, cnt, 2, 4 * p->nformulas, nullptr, s));
     for (uint32_t i = 0; i < p->nformulas; ++i) {
+      if (count && p->tiers.order[i] >= count) continue;
       const int ls = i < p->tiers.count_a ? p->tiers.ls_a : p->tiers.ls_b;
       int rc = enqueue_fast(p->ds, p->db, p->n, p->nvars, ls, 0, true, 1, 0, nf, key, cnt, false,
                             p->db.queue, s, p->ipw, 0, i, false, p->nformulas);
@@ -800,8 +804,9 @@ static int plan_enqueue_plain(KripkePlan* p, kripke_census_result* d_out, hipStr
 // frames; the choice is cached in a small JSON file keyed by device, shape
 // and a hash of the compiled batch.
 static int plan_enqueue_any(KripkePlan* p, kripke_census_result* d_out, hipStream_t s,
-                            uint64_t frames) {
-  return p->plain ? plan_enqueue_plain(p, d_out, s, frames) : plan_enqueue(p, d_out, s, frames);
+                            uint64_t frames, uint32_t count = 0) {
+  return p->plain ? plan_enqueue_plain(p, d_out, s, frames, count)
+                  : plan_enqueue(p, d_out, s, frames);
 }
 
 static std::string tune_key(const KripkePlan* p) {
@@ -896,6 +901,10 @@ static int tune_plan(KripkePlan* p, const char* path) {
   kripke_census_result* trial_out = trial.out;
   hipEvent_t e0 = trial.e0, e1 = trial.e1;
   const uint64_t slice = std::min<uint64_t>(1ull << (p->n * p->n), 1ull << 20);
+  // the per-formula form is timed on the batch's first 256 formulas (its cost is one
+  // launch per formula, so the whole batch would cost 24 x nformulas launches)
+  const uint32_t count = p->plain ? std::min<uint32_t>(p->nformulas, 256) : 0;
+  const bool verbose = getenv("KRIPKE_TUNE_LOG") && atoi(getenv("KRIPKE_TUNE_LOG"));
   double best = 1e300;
   int best_ls = p->ls, best_ipw = p->ipw;
   // every candidate computes the same slice; its results must be identical
@@ -908,10 +917,10 @@ static int tune_plan(KripkePlan* p, const char* path) {
     for (int w : {4, 16, 64}) {
       p->ls = l;
       p->ipw = w;
-      int rc = plan_enqueue_any(p, trial_out, p->cap, slice);  // warm
+      int rc = plan_enqueue_any(p, trial_out, p->cap, slice, count);  // warm
       if (rc) return rc;
       KR_HIP(hipEventRecord(e0, p->cap));
-      if ((rc = plan_enqueue_any(p, trial_out, p->cap, slice))) return rc;
+      if ((rc = plan_enqueue_any(p, trial_out, p->cap, slice, count))) return rc;
       KR_HIP(hipEventRecord(e1, p->cap));
       KR_HIP(hipEventSynchronize(e1));
       float ms = 0;
@@ -924,6 +933,9 @@ static int tune_plan(KripkePlan* p, const char* path) {
                                           " ipw=" + std::to_string(w) +
                                           " disagrees with the first candidate");
       }
+      if (verbose)
+        fprintf(stderr, "[kripke tune] %s ls=%d ipw=%d: %.3f ms on %llu frames\n",
+                p->plain ? "per-formula" : "batched", l, w, ms, (unsigned long long)slice);
       if (ms < best) {
         best = ms;
         best_ls = l;
@@ -1241,7 +1253,9 @@ int kripke_plan_create(const uint8_t* code, const uint32_t* offsets, uint32_t nf
   }
   if (tune_cache && p->ls >= 0 && !getenv("KRIPKE_SETS_LOG2") &&
       (rc = tune_plan(p, tune_cache))) {
-    kripke_plan_destroy(p);
+    const std::string msg = g_err;  // freeing the plan must not clear the message
+    plan_free(p);
+    g_err = msg;
     return rc;
   }
   *plan = p;
@@ -1305,10 +1319,7 @@ int kripke_plan_launch(void* plan, kripke_census_result* d_out, void* stream) {
   return KRIPKE_OK;
 }
 
-int kripke_plan_destroy(void* plan) {
-  g_err.clear();
-  auto* p = static_cast<KripkePlan*>(plan);
-  if (!p) return KRIPKE_OK;
+static void plan_free(KripkePlan* p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap) {
@@ -1317,6 +1328,11 @@ int kripke_plan_destroy(void* plan) {
     (void)hipStreamDestroy(p->cap);
   }
   delete p;
+}
+
+int kripke_plan_destroy(void* plan) {
+  g_err.clear();
+  if (plan) plan_free(static_cast<KripkePlan*>(plan));
   return KRIPKE_OK;
 }
 

@@ -255,7 +255,8 @@ def run(n_test=10000, n_train=10000, universe_pairs=5_500_000, train_pairs=5_500
         budget=1_000_000, steps=2000, panel_frames=4096, log=print, details=False):
     """The full protocol; returns a dict of hit counts and timings.  With details, also
     the verified pairs (host arrays) under "details": canonical pair codes of the verified
-    union, hit flags, agreement flags, separating keys and the n they were found at."""
+    union and their (sorted) indices in the test universe, hit flags, agreement flags,
+    separating keys, the n they were found at, and each ranking as universe indices."""
     torch = _t()
     t0 = time.time()
     rec = {}
@@ -339,7 +340,8 @@ def run(n_test=10000, n_train=10000, universe_pairs=5_500_000, train_pairs=5_500
                           "late_splits": int(hit_u.sum()),
                           "late_splits_five_world": int(agree5.sum())}
     if details:
-        rec["details"] = {"pairs": K.as_u64(u_te[union]).copy(), "hit": hit_u,
+        rec["details"] = {"pairs": K.as_u64(u_te[union]).copy(), "union_idx": union_h,
+                          "hit": hit_u,
                           "agree5": agree5,
                           "agree4": info["agree4"], "keys": info["keys"], "n": info["n"],
                           "panel": panel, "rankings": {k: v.cpu().numpy()

@@ -37,7 +37,9 @@ def config4_pairs(count: int = 20_000, pool: int = 200_000, log=None):
     cand = bucket_pairs(K.as_u64(sig))
     del sig
     torch.cuda.empty_cache()
-    ver = Verifier(fs, panel={})
+    if log:
+        log(f"C4 pairs: {len(cand)} same-signature candidates from {pool} formulas")
+    ver = Verifier(fs, panel={}, log=log)
     agree = ver.agree_through(cand[:, 0], cand[:, 1])
     surv = cand[agree]
     designed = I.config4_designed_pairs()

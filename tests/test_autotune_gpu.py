@@ -87,3 +87,26 @@ def test_plain_baseline_matches(kr):
         assert _matches(_launch(kr, plan, len(fs)), ref)
     finally:
         kr.kripke_plan_destroy(plan)
+
+
+def test_per_formula_tuner_on_a_subset_of_a_large_batch(kr, tmp_path, monkeypatch):
+    """A per-formula plan over more than 256 formulas is tuned on the batch's first 256;
+    the candidates' tiers (which formulas a variant's stack holds) differ, yet every
+    candidate times the same formulas and must agree, and the tuned plan reproduces the
+    single-class censuses on the whole batch."""
+    monkeypatch.delenv("KRIPKE_SETS_LOG2", raising=False)
+    deep = [I.parse("(((<>p & []q) | (<>~q & []~p)) <-> ((<>(p & q) & [](p | ~q)) | "
+                    "(<>[]p & []<>q)))")] * 4
+    fs = I.config3_formulas()[:300] + deep
+    code, offs = I.pack(fs)
+    slots = kr.kripke_program_stats(code, offs, 2)[:, 4]
+    assert slots.max() >= 2  # the deep programs need a second stack slot: tiers differ
+    ref = _reference(kr, fs)
+    cache = str(tmp_path / "tune.json")
+    plan = kr.kripke_plan_create(code, offs, 5, 0xF | kr.KRIPKE_PLAN_PLAIN, 2, tune_cache=cache)
+    try:
+        assert _matches(_launch(kr, plan, len(fs)), ref)
+    finally:
+        kr.kripke_plan_destroy(plan)
+    key = next(iter(json.load(open(cache))))
+    assert key.endswith("/per-formula") and "/B304/" in key

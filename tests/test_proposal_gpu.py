@@ -237,7 +237,8 @@ def test_mlp_training_reduces_loss(kr):
 # ------------------------------------------------------------ pipeline
 def test_learned_ranking_beats_plain_and_hits_are_certified(kr, orc):
     """The protocol at reduced scale: the learned ranking finds more verified late splits
-    than plain canonical enumeration at equal budget, and the oracle confirms a sample of
+    than plain canonical enumeration and than the signature Hamming ranking at equal
+    budget, and the oracle confirms a sample of
     the verdicts: a hit agrees through 4 worlds and its key is the panel's first
     separating model; a rejected pair has a countermodel within 4 worlds; a pair the
     panel does not separate has no separating model on the 6-world panel nor on the
@@ -248,6 +249,19 @@ def test_learned_ranking_beats_plain_and_hits_are_certified(kr, orc):
                 budget=20_000, steps=300, panel_frames=256, log=lambda m: None, details=True)
     assert rec["learned"]["hits"] > 2 * rec["plain"]["hits"], rec
     d = rec["details"]
+    # hits of each ranking within its first b proposals (rankings are stable, so a
+    # smaller budget's selection is a prefix)
+    at = {}
+    for name, ids in d["rankings"].items():
+        hit = d["hit"][np.searchsorted(d["union_idx"], ids)]
+        at[name] = {b: int(hit[:b].sum()) for b in (500, 1000, 2000, 5000, 10000, 20000)}
+    print("hits at budget:", at, flush=True)
+    # the trained scorer also ranks ahead of the signature-distance baseline: it holds at
+    # least as many hits at every budget up to 10^4 and a clear margin at 5,000 (measured:
+    # 565 against 383; every step of the protocol is seeded and deterministic)
+    for b in (500, 1000, 2000, 5000, 10000):
+        assert at["learned"][b] >= at["hamming"][b], (b, at)
+    assert at["learned"][5000] > 1.2 * at["hamming"][5000], at
     test = I.retrieval_corpus(I.SEED_C5_TEST, 2000, n_words=400)
     ia = (d["pairs"] >> np.uint64(32)).astype(np.int64)
     ib = (d["pairs"] & np.uint64(0xFFFFFFFF)).astype(np.int64)
