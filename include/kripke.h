@@ -109,6 +109,32 @@ int kripke_census_range(const uint8_t *code, const uint32_t *offsets, uint32_t n
                         void *stream);
 
 /*
+ * kripke_census_range_static -- kripke_census_range for callers that cannot
+ * allocate device memory (tight serving loops, hosts that forbid device
+ * allocation during a run): same arguments, same results, but no
+ * hipMalloc/hipFree or allocating library call is made.  Its working
+ * memory (the compiled programs, their launch order and two work-queue
+ * counters) lives in one fixed static device array of about 1.1 MB per GPU,
+ * held from the first call on that GPU until the process ends.
+ * Limits beyond kripke_census_range's: classes K and T only (S4 and S5 need
+ * the frame lists the library allocates; KRIPKE_EINVAL), at most
+ * KRIPKE_STATIC_MAX_FORMULAS formulas and KRIPKE_STATIC_MAX_CODE bytes of
+ * compiled programs (each program compiles to at most 2 * length + 2 micro-ops,
+ * padded to 8 bytes; KRIPKE_ELIMIT).
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on the same GPU (on different streams or threads) race and give undefined
+ * results; calls serialised on one stream are safe.  The call waits for its
+ * host-to-device copies (a stream synchronisation) before enqueuing kernels,
+ * so it cannot be recorded into a graph under stream capture.
+ */
+#define KRIPKE_STATIC_MAX_FORMULAS 8192u
+#define KRIPKE_STATIC_MAX_CODE (1u << 20)
+int kripke_census_range_static(const uint8_t *code, const uint32_t *offsets,
+                               uint32_t nformulas, uint32_t n, uint32_t cls, uint32_t nvars,
+                               uint64_t frame_begin, uint64_t frame_end, uint32_t flags,
+                               kripke_census_result *d_out, void *stream);
+
+/*
  * kripke_frame_validity -- per-frame validity maps (Section 10: Val_N(phi),
  * the set of frames on which phi holds at every world under every valuation,
  * the input of frame-correspondence recovery).  For every formula and every

@@ -506,6 +506,60 @@ int upload_order(const Tiering& t, uint32_t* d_order, hipStream_t s) {
 
 }  // namespace
 
+// ------------------------------------------------- allocation-free census
+// Fixed device scratch of kripke_census_range_static: the two work-queue
+// counters, the program offsets, the launch order and the micro-op code of one
+// batch, at the offsets below.  Every device holds its own copy until the
+// process ends.  Host code never names the array in a device context: it uses
+// the address hipGetSymbolAddress returns for the current device.
+constexpr uint64_t kStQueue = 0;  // 2 x u64
+constexpr uint64_t kStOff = 256;  // u32[max formulas + 1]
+constexpr uint64_t kStOrder =
+    kStOff + ((4ull * (KRIPKE_STATIC_MAX_FORMULAS + 1) + 255) & ~255ull);  // u32[max + 1]
+constexpr uint64_t kStCode =
+    kStOrder + ((4ull * (KRIPKE_STATIC_MAX_FORMULAS + 1) + 255) & ~255ull);
+constexpr uint64_t kStBytes = kStCode + KRIPKE_STATIC_MAX_CODE;
+
+static __device__ __align__(256) uint8_t scratch[kStBytes];
+
+namespace {
+
+std::map<int, uint8_t*> g_scratch;  // device ordinal -> address of its `scratch`
+
+// Address of the current device's scratch, looked up once per device.
+int static_scratch(uint8_t** out) {
+  int dev = 0;
+  KR_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_scratch.find(dev);
+  if (it == g_scratch.end()) {
+    void* p = nullptr;
+    KR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(KRIPKE_EHIP, "hipGetSymbolAddress returned no address for scratch");
+    it = g_scratch.emplace(dev, static_cast<uint8_t*>(p)).first;
+  }
+  *out = it->second;
+  return KRIPKE_OK;
+}
+
+// The DeviceBatch of a compiled batch placed in the static scratch; the
+// order area receives `order` (the tier order of the fast path or the batch's
+// cost order).  Waits for the copies: the host vectors die with the caller.
+int stage_static(uint8_t* base, const MicroBatch& mb, const std::vector<uint32_t>& order,
+                 DeviceBatch* db, hipStream_t s) {
+  db->queue = reinterpret_cast<unsigned long long*>(base + kStQueue);
+  db->uoff = reinterpret_cast<uint32_t*>(base + kStOff);
+  db->order = reinterpret_cast<uint32_t*>(base + kStOrder);
+  db->ucode = base + kStCode;
+  KR_HIP(hipMemcpyAsync(db->ucode, mb.code.data(), mb.code.size(), hipMemcpyHostToDevice, s));
+  KR_HIP(hipMemcpyAsync(db->uoff, mb.off.data(), mb.off.size() * 4, hipMemcpyHostToDevice, s));
+  KR_HIP(hipMemcpyAsync(db->order, order.data(), order.size() * 4, hipMemcpyHostToDevice, s));
+  KR_HIP(hipStreamSynchronize(s));
+  return KRIPKE_OK;
+}
+
+}  // namespace
+
 static int check_range_args(uint32_t nformulas, uint32_t n, uint32_t cls, uint32_t nvars,
                      uint64_t frame_begin, uint64_t frame_end, uint32_t flags,
                      const kripke_census_result* d_out) {
@@ -575,6 +629,50 @@ int kripke_census_range(const uint8_t* code, const uint32_t* offsets, uint32_t n
                     false, db.queue, s);
   int rc2 = release(&db, s);
   return rc ? rc : rc2;
+}
+
+int kripke_census_range_static(const uint8_t* code, const uint32_t* offsets,
+                               uint32_t nformulas, uint32_t n, uint32_t cls, uint32_t nvars,
+                               uint64_t frame_begin, uint64_t frame_end, uint32_t flags,
+                               kripke_census_result* d_out, void* stream) {
+  g_err.clear();
+  int rc = check_range_args(nformulas, n, cls, nvars, frame_begin, frame_end, flags, d_out);
+  if (rc) return rc;
+  if (cls > KRIPKE_T)
+    return fail(KRIPKE_EINVAL, "the static-scratch census supports classes K and T only");
+  if (nformulas > KRIPKE_STATIC_MAX_FORMULAS)
+    return fail(KRIPKE_ELIMIT, "the static-scratch census takes at most " +
+                                   std::to_string(KRIPKE_STATIC_MAX_FORMULAS) + " formulas");
+  MicroBatch mb;
+  if ((rc = compile_batch(code, offsets, nformulas, nvars, (int)n, false, &mb))) return rc;
+  if (mb.code.size() > KRIPKE_STATIC_MAX_CODE)
+    return fail(KRIPKE_ELIMIT, "compiled batch of " + std::to_string(mb.code.size()) +
+                                   " bytes exceeds the static program area of " +
+                                   std::to_string(KRIPKE_STATIC_MAX_CODE) + " bytes");
+  DeviceState* ds = nullptr;
+  if ((rc = device_state(&ds))) return rc;
+  uint8_t* base = nullptr;
+  if ((rc = static_scratch(&base))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  auto* key = reinterpret_cast<unsigned long long*>(&d_out[0].first_key);
+  auto* cnt = reinterpret_cast<unsigned long long*>(&d_out[0].fail_count);
+  const bool decide = flags == KRIPKE_DECIDE;
+  const int mode = cls == KRIPKE_K ? 0 : 1;
+  Tiering tiers;
+  DeviceBatch db;
+  if (pick_tiers(mb, (int)n, (int)nvars, mode, false, &tiers)) {
+    const uint64_t p0 = mode == 0 ? frame_begin : t_rank(frame_begin, (int)n);
+    const uint64_t p1 = mode == 0 ? frame_end : t_rank(frame_end, (int)n);
+    if ((rc = stage_static(base, mb, tiers.order, &db, s))) return rc;
+    return enqueue_tiered(ds, db, tiers, (int)n, (int)nvars, mode, false, nformulas, p0, p1, key,
+                          cnt, decide, db.queue, s, 16);
+  }
+  // K and T scans need no class list, so make_scan allocates nothing here
+  Scan sc;
+  if ((rc = make_scan(ds, (int)n, (int)cls, frame_begin, frame_end, &sc))) return rc;
+  if ((rc = stage_static(base, mb, mb.order, &db, s))) return rc;
+  return enqueue_scan(ds, db, sc, (int)n, (int)nvars, nformulas, key, cnt, 2, decide, false,
+                      db.queue, s);
 }
 
 int kripke_frame_validity(const uint8_t* code, const uint32_t* offsets, uint32_t nformulas,

@@ -47,6 +47,8 @@ def lib():
         sig = {
             "kripke_census": [u8p, u32p, u32, u32, u32, u32, vp, vp],
             "kripke_census_range": [u8p, u32p, u32, u32, u32, u32, u64, u64, u32, vp, vp],
+            "kripke_census_range_static": [u8p, u32p, u32, u32, u32, u32, u64, u64, u32, vp,
+                                           vp],
             "kripke_split": [u8p, u32, u8p, u32, vp, u64, u32, u32, vp, vp],
             "kripke_frame_validity": [u8p, u32p, u32, u32, u32, vp, vp],
             "kripke_split_batch": [u8p, u32p, u32, vp, u64, u32, u32, vp, vp],
@@ -127,6 +129,15 @@ def kripke_census_range(code, offsets, n, cls, nvars, frame_begin, frame_end, fl
     o, op = _host_u32(offsets)
     _check(lib().kripke_census_range(cp, op, len(o) - 1, n, cls, nvars, frame_begin, frame_end,
                                      flags, _ptr(d_out), _stream(stream)))
+
+
+def kripke_census_range_static(code, offsets, n, cls, nvars, frame_begin, frame_end, flags,
+                               d_out, stream=None):
+    """kripke_census_range without device allocation (fixed static scratch; K and T)."""
+    c, cp = _host_u8(code)
+    o, op = _host_u32(offsets)
+    _check(lib().kripke_census_range_static(cp, op, len(o) - 1, n, cls, nvars, frame_begin,
+                                            frame_end, flags, _ptr(d_out), _stream(stream)))
 
 
 def kripke_frame_validity(code, offsets, n, nvars, d_bits, stream=None):
