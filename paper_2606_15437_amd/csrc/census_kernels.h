@@ -36,8 +36,9 @@ struct CensusArgs {
 
 // Arguments of the wave-uniform-frame kernel.  Positions are frame indices
 // (mode 0, class K), ranks of reflexive frames (mode 1, class T) or indices
-// into a list of successor rows (mode 2); a block holds 2^fast_block_log2()
-// consecutive positions.
+// into a list of successor rows (mode 2: one list frame per block; mode 3:
+// two, one per half-wave); a block holds 2^fast_block_log2() consecutive
+// positions.
 struct FastArgs {
   const uint8_t* ucode;
   const uint32_t* uoff;
@@ -53,7 +54,7 @@ struct FastArgs {
   uint32_t out_stride;
   uint64_t class_stride;
   uint32_t decide;
-  const uint32_t* list_succ;    // mode 2: successor rows [positions][n]
+  const uint32_t* list_succ;    // modes 2, 3: successor rows [positions][n]
   uint32_t* valid_bits;         // optional frame-validity maps [nformulas][valid_words],
   uint64_t valid_words;         // bit p = no countermodel on position p (mode 0)
 };

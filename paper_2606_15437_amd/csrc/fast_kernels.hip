@@ -27,6 +27,11 @@
 // block is ONE list frame, so every relation word is wave-uniform and comes
 // from the frame's successor rows; the set bits then index valuation bits
 // 11 .. 11+LS-1 (between the lane bits and the chunk loop) instead of frames.
+// Where a frame has only 2^12 valuations (six worlds, two variables) a wave
+// would carry just two sets per interpreter dispatch; mode LIST2 instead puts
+// two list frames in a block, one per half-wave (lane bit 5 is a frame bit,
+// the relation words are per-lane values), with four sets over valuation bits
+// 10 and 11, so each dispatch and each relation decode serves two frames.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -66,7 +71,7 @@ __host__ __device__ constexpr int free_rank(int p) {
 
 template <int N, int MODE, int LF, int LS>
 __host__ __device__ constexpr int role(int p) {
-  if (MODE == 2) return R_UNIFORM;
+  if (MODE >= 2) return R_UNIFORM;
   if (MODE == 1 && p % (N + 1) == 0) return R_ONE;
   const int r = free_rank<N, MODE>(p);
   return r < LF ? R_LANE : r < LF + LS ? R_SET : R_UNIFORM;
@@ -92,16 +97,21 @@ __host__ __device__ constexpr bool list_n8_four_sets(bool list, int n, int ls) {
 
 template <int N, int NV, int LS, int MODE>
 struct Geo {
-  static constexpr bool LIST = MODE == 2;
+  static constexpr bool LIST = MODE >= 2;
+  // two list frames per block, one per half-wave (their relation words are
+  // per-lane values), for lists whose frames have too few valuations to fill
+  // a wave with several sets
+  static constexpr bool LIST2 = MODE == 3;
   static constexpr int V = N * NV;
-  static constexpr int LV = V >= 11 ? 6 : (V > 5 ? V - 5 : 0);  // lane valuation bits
+  static constexpr int LV = LIST2 ? 5 : V >= 11 ? 6 : (V > 5 ? V - 5 : 0);  // lane valuation bits
   static constexpr int LF = 6 - LV;                              // lane frame bits
   static constexpr int S = 1 << LS;                              // sets per lane
   static constexpr int SV = LIST ? LS : 0;                       // set bits that are valuation bits
-  static constexpr int B = LIST ? 0 : LF + LS;                   // log2 frames per block
-  static constexpr int CHB = V > 11 + SV ? V - 11 - SV : 0;      // valuation chunk bits
+  static constexpr int B = LIST2 ? 1 : LIST ? 0 : LF + LS;       // log2 frames per block
+  static constexpr int CHB = V > 5 + LV + SV ? V - 5 - LV - SV : 0;  // valuation chunk bits
   // stack slots in registers (one at the eight-world four-set list variant)
-  static constexpr int DS = LS == 0 ? 4 : (LS <= 2 && !list_n8_four_sets(LIST, N, LS)) ? 2 : 1;
+  static constexpr int DS =
+      LS == 0 ? 4 : (LS <= 2 && !list_n8_four_sets(LIST, N, LS) && !LIST2) ? 2 : 1;
   // + slots held wholly in LDS; none at LS = 3 (40 KB per block would cap
   // residency at three blocks per CU) nor in the eight-world four-set list
   // variant (its LDS stack sets already take 16 KB per block): programs
@@ -112,7 +122,7 @@ struct Geo {
   // half the rate of one with vector operands only, and the modal terms are
   // most of the work.  Census modes hold every row; list mode (n^2 uniform
   // words) holds the rows that fit its register budget, the rest stay scalar.
-  static constexpr int RV_ROWS = !LIST ? N : list_rows(N, LS);
+  static constexpr int RV_ROWS = !LIST || LIST2 ? N : list_rows(N, LS);
   static constexpr bool RUV = RV_ROWS > 0;
   static constexpr int WPE = LS >= 3 || LIST ? 4 : 1;
   // sets of each register stack slot that live in registers; the others sit
@@ -519,8 +529,9 @@ __device__ __forceinline__ uint64_t candidate(const Ctx<N, NV, LS, MODE>& c, int
     if (!((c.acc[s][w] >> j) & 1u)) world = w;
   // list mode: the key's frame field is the list position, and the set is a
   // valuation field
-  const uint64_t pos = G::LIST ? blk
-                               : (blk << G::B) | ((uint64_t)s << G::LF) | (uint64_t)(lane >> G::LV);
+  const uint64_t pos = G::LIST2  ? (blk << G::B) | (uint64_t)(lane >> G::LV)
+                       : G::LIST ? blk
+                                 : (blk << G::B) | ((uint64_t)s << G::LF) | (uint64_t)(lane >> G::LV);
   const uint64_t frame = MODE == 1 ? refl_frame(pos, N) : pos;
   const uint64_t val = ((uint64_t)chunk << (5 + G::LV + G::SV)) |
                        (G::LIST ? (uint64_t)s << (5 + G::LV) : 0ull) |
@@ -536,7 +547,7 @@ __attribute__((amdgpu_waves_per_eu(Geo<N, NV, LS, MODE>::WPE)))
 void census_fast(FastArgs a) {
   using G = Geo<N, NV, LS, MODE>;
   static_assert(G::V >= 5, "fast kernel needs n * nvars >= 5");
-  static_assert(!G::LIST || (G::V >= 11 + LS && !FUSED),
+  static_assert(!G::LIST || (G::V >= 5 + G::LV + LS && !FUSED),
                 "list mode needs the lane and set bits to be valuation bits");
   __shared__ uint32_t sprog[4][kMaxMicro / 4 + 4];
   __shared__ uint32_t sspill[4][G::LDS_WORDS > 0 ? G::LDS_WORDS * 64 : 1];
@@ -622,8 +633,27 @@ void census_fast(FastArgs a) {
 
     for (uint64_t blk = b0; blk < b1 && !done; ++blk) {
       const uint64_t pbase = blk << G::B;
-      uint64_t base;
-      if constexpr (G::LIST) {
+      uint64_t base = 0;
+      if constexpr (G::LIST2) {
+        // each half-wave's frame (position pbase | lane_pos; a position past the
+        // list end, in a ragged last block, loads the last frame and is masked
+        // out of the failure test) as per-lane relation words, one signed
+        // bit-field extract per word from the lane's successor rows
+        uint64_t fp = pbase | lane_pos;
+        if (fp >= a.pos_end) fp = a.pos_end - 1;
+        const uint32_t* r = a.list_succ + fp * N;
+        uint32_t row[N];
+#pragma unroll
+        for (int w = 0; w < N; ++w) row[w] = r[w];
+#pragma unroll
+        for (int w = 0; w < N; ++w)
+#pragma unroll
+          for (int v = 0; v < N; ++v) {
+            uint32_t x;
+            asm volatile("v_bfe_i32 %0, %1, %2, 1" : "=v"(x) : "v"(row[w]), "i"(v));
+            c.ru[w][v] = x;
+          }
+      } else if constexpr (G::LIST) {
         // the list frame's successor rows, wave-uniform
         // the list is read-only for the kernel's lifetime: reading it through
         // the constant address space gives scalar loads straight into SGPRs
@@ -639,7 +669,7 @@ void census_fast(FastArgs a) {
       // the relation bits in vector registers, expanded there by one signed
       // bit-field extract per word (opaque, so the words stay vector values)
       uint32_t vbase[2] = {0u, 0u};
-      if constexpr (G::RUV) {
+      if constexpr (G::RUV && !G::LIST2) {
         asm volatile("v_mov_b32 %0, %1" : "=v"(vbase[0]) : "s"((uint32_t)base));
         if constexpr (N * G::RV_ROWS > 32)
           asm volatile("v_mov_b32 %0, %1" : "=v"(vbase[1]) : "s"((uint32_t)(base >> 32)));
@@ -649,7 +679,7 @@ void census_fast(FastArgs a) {
 #pragma unroll
         for (int v = 0; v < N; ++v) {
           const int p = w * N + v;
-          if (role<N, MODE, G::LF, LS>(p) != R_UNIFORM) continue;
+          if (G::LIST2 || role<N, MODE, G::LF, LS>(p) != R_UNIFORM) continue;
           if (w < G::RV_ROWS) {
             uint32_t r;
             asm volatile("v_bfe_i32 %0, %1, %2, 1" : "=v"(r) : "v"(vbase[p >> 5]), "i"(p & 31));
@@ -661,7 +691,7 @@ void census_fast(FastArgs a) {
           }
         }
       // valid (lane, set) pairs: positions inside [pos_begin, pos_end)
-      const bool ragged = !G::LIST && (blk == rag_lo || blk == rag_hi);
+      const bool ragged = (!G::LIST || G::LIST2) && (blk == rag_lo || blk == rag_hi);
       // class levels of the block's frames; consumed only after evaluation,
       // so the scalar load overlaps the interpreter
       uint32_t lvl_raw = 0;
@@ -692,7 +722,7 @@ void census_fast(FastArgs a) {
           for (int w = 0; w < N; ++w) all &= c.acc[s][w];
           uint32_t fail = ~all;  // an all-fail program's accumulator is zero
           if (ragged) {
-            const uint64_t pos = pbase | ((uint64_t)s << G::LF) | lane_pos;
+            const uint64_t pos = pbase | (G::LIST ? 0ull : (uint64_t)s << G::LF) | lane_pos;
             if (pos < a.pos_begin || pos >= a.pos_end) fail = 0;
           }
           return fail;
@@ -750,26 +780,35 @@ void census_fast(FastArgs a) {
         }
         // one ballot per block while no key is known; then the least key lies in
         // the first failing set (sets follow frame positions, or, in list mode,
-        // valuation bits above the lane bits)
+        // valuation bits above the lane bits).  With two list frames per block
+        // the first half-wave's frame comes first whatever its set, so the sets
+        // are searched on its lanes first, then on the whole wave.
         if (key[0] == ~0ull && __ballot(anyfail != 0)) {
           bool found = false;
 #pragma unroll
-          for (int s = 0; s < G::S; ++s) {
-            if (!found) {
-              const uint32_t fail = fail_of(s);
-              const uint64_t bal = __ballot(fail != 0);
-              if (bal) {
-                const uint64_t k = candidate(c, s, fail, bal, blk, chunk, lane);
-                best[0] = k < best[0] ? k : best[0];
-                found = true;
+          for (int half = 0; half < (G::LIST2 ? 2 : 1); ++half) {
+            const uint64_t lanes = G::LIST2 && half == 0 ? 0xFFFFFFFFull : ~0ull;
+#pragma unroll
+            for (int s = 0; s < G::S; ++s) {
+              if (!found) {
+                const uint32_t fail = fail_of(s);
+                const uint64_t bal = __ballot(fail != 0) & lanes;
+                if (bal) {
+                  const uint64_t k = candidate(c, s, fail, bal, blk, chunk, lane);
+                  best[0] = k < best[0] ? k : best[0];
+                  found = true;
+                }
               }
             }
           }
         }
         // list mode: chunks run in increasing valuation order inside one
         // frame, so the first chunk with a failure holds the frame's least key
+        // (with two frames per block, only if that failure is in the first)
         if constexpr (G::LIST)
-          if (a.decide && best[0] != ~0ull) break;
+          if (a.decide && best[0] != ~0ull &&
+              (!G::LIST2 || (best[0] >> (G::V + 4)) == pbase))
+            break;
       }
 #pragma unroll
       for (int k = 0; k < NC; ++k)
@@ -867,6 +906,8 @@ const Entry kTable[] = {
     KR_E(6, 2, 0, 2, false), KR_E(6, 2, 1, 2, false),
     KR_E(7, 2, 0, 2, false), KR_E(7, 2, 1, 2, false), KR_E(7, 2, 2, 2, false),
     KR_E(8, 2, 0, 2, false), KR_E(8, 2, 1, 2, false), KR_E(8, 2, 2, 2, false),
+    // two frames per block
+    KR_E(6, 2, 2, 3, false),
 };
 
 const Entry* find(int n, int nvars, int ls, int mode, bool fused) {
@@ -884,6 +925,7 @@ bool fast_available(int n, int nvars, int ls, int mode, bool fused) {
 
 int fast_block_log2(int n, int nvars, int ls, int mode) {
   if (mode == 2) return 0;
+  if (mode == 3) return 1;
   const int V = n * nvars;
   const int lv = V >= 11 ? 6 : (V > 5 ? V - 5 : 0);
   return 6 - lv + ls;

@@ -382,11 +382,13 @@ struct Tiering {
   std::vector<uint32_t> order;
   uint32_t count_a = 0;
   int ls_a = -1, ls_b = -1;
+  int mode_a = -1, mode_b = -1;  // kernel mode of each tier
 };
 
 bool make_tiers(const MicroBatch& mb, int n, int nvars, int mode, bool fused, int ls,
                 Tiering* t) {
   if (ls < 0 || !fast_available(n, nvars, ls, mode, fused)) return false;
+  t->mode_a = t->mode_b = mode;
   t->order.clear();
   int max_b = 0;
   for (uint32_t f : mb.order)
@@ -400,10 +402,15 @@ bool make_tiers(const MicroBatch& mb, int n, int nvars, int mode, bool fused, in
   t->ls_a = ls;
   t->ls_b = -1;
   if (t->count_a < t->order.size()) {
-    for (int l = 2; l >= 0 && t->ls_b < 0; --l)
-      if (fast_available(n, nvars, l, mode, fused) &&
-          max_b <= fast_stack_slots(n, nvars, l, mode, fused))
-        t->ls_b = l;
+    // the deeper programs: the widest variant of the same mode that holds them;
+    // two-frame list blocks fall back to one-frame list blocks (same keys)
+    for (int m : {mode, mode == 3 ? 2 : mode})
+      for (int l = 2; l >= 0 && t->ls_b < 0; --l)
+        if (fast_available(n, nvars, l, m, fused) &&
+            max_b <= fast_stack_slots(n, nvars, l, m, fused)) {
+          t->ls_b = l;
+          t->mode_b = m;
+        }
     if (t->ls_b < 0) return false;
   }
   return true;
@@ -433,7 +440,7 @@ int enqueue_fast(DeviceState* ds, const DeviceBatch& db, int n, int nvars, int l
   // row_formulas: formulas per class row of the output (the whole batch, which
   // a tier launch covers only part of); out_stride: 64-bit words between the
   // keys of consecutive formulas (2 for census results, 1 for split keys);
-  // list_succ: the frame list of mode 2
+  // list_succ: the frame list of modes 2 and 3
   if (row_formulas == 0) row_formulas = nformulas;
   FastArgs a{};
   a.ucode = db.ucode;
@@ -479,8 +486,9 @@ int enqueue_fast(DeviceState* ds, const DeviceBatch& db, int n, int nvars, int l
   return KRIPKE_OK;
 }
 
-// Enqueue a tiered fast census: one init, then one launch per tier.  The
-// device order array must already hold t.order.
+// Enqueue a tiered fast census: one init, then one launch per tier, each in
+// its tier's mode (`mode` names the position space of p0, p1: both tiers
+// share it).  The device order array must already hold t.order.
 int enqueue_tiered(DeviceState* ds, const DeviceBatch& db, const Tiering& t, int n, int nvars,
                    int mode, bool fused, uint32_t nformulas, uint64_t p0, uint64_t p1,
                    unsigned long long* key, unsigned long long* cnt, bool decide,
@@ -488,11 +496,12 @@ int enqueue_tiered(DeviceState* ds, const DeviceBatch& db, const Tiering& t, int
                    const uint32_t* list_succ = nullptr, uint32_t* valid_bits = nullptr,
                    uint64_t valid_words = 0) {
   KR_HIP(launch_init(key, cnt, out_stride, fused ? 4 * nformulas : nformulas, nullptr, s));
-  int rc = enqueue_fast(ds, db, n, nvars, t.ls_a, mode, fused, t.count_a, p0, p1, key, cnt, decide,
-                        queues, s, ipw, 0, 0, false, nformulas, out_stride, list_succ,
+  (void)mode;
+  int rc = enqueue_fast(ds, db, n, nvars, t.ls_a, t.mode_a, fused, t.count_a, p0, p1, key, cnt,
+                        decide, queues, s, ipw, 0, 0, false, nformulas, out_stride, list_succ,
                         valid_bits, valid_words);
   if (rc || t.count_a == (uint32_t)t.order.size()) return rc;
-  return enqueue_fast(ds, db, n, nvars, t.ls_b, mode, fused,
+  return enqueue_fast(ds, db, n, nvars, t.ls_b, t.mode_b, fused,
                       (uint32_t)t.order.size() - t.count_a, p0, p1, key, cnt, decide, queues + 1,
                       s, ipw, 0, t.count_a, false, nformulas, out_stride, list_succ,
                       valid_bits, valid_words);
@@ -783,10 +792,14 @@ int kripke_split_batch(const uint8_t* code, const uint32_t* offsets, uint32_t np
   }
   // wave-uniform list frames when the lanes can hold valuations only;
   // KRIPKE_SPLIT_GENERIC=1 forces the per-lane-frame kernel (for comparison)
+  // (two list frames per block where a frame's valuations fill only two sets
+  // of a wave; KRIPKE_SPLIT_ONE_FRAME=1 keeps one frame per block)
   const char* force_generic = getenv("KRIPKE_SPLIT_GENERIC");
+  const char* one_frame = getenv("KRIPKE_SPLIT_ONE_FRAME");
   Tiering tiers;
   if (!(force_generic && atoi(force_generic)) &&
-      pick_tiers(mb, (int)n, (int)nvars, 2, false, &tiers)) {
+      ((!(one_frame && atoi(one_frame)) && pick_tiers(mb, (int)n, (int)nvars, 3, false, &tiers)) ||
+       pick_tiers(mb, (int)n, (int)nvars, 2, false, &tiers))) {
     if ((rc = upload(mb, &db, 2, s))) return rc;
     if ((rc = upload_order(tiers, db.order, s))) return rc;
     rc = enqueue_tiered(ds, db, tiers, (int)n, (int)nvars, 2, false, npairs, 0, nframes,
