@@ -198,6 +198,147 @@ hipError_t gemm(LA A, LB B, EPI E, uint32_t M, uint32_t N, uint32_t K, hipStream
   return gemm_tiles<1, 1>(A, B, E, M, N, K, s);
 }
 
+// ------------------------------------------------------ layer-1 forward
+// C[m][n] = sum_k x_m(k) W1[n][k] for the scoring and training forwards of
+// large batches: M pairs x 512 outputs x K = 8,192, where x_m(k) is bit k of
+// [sig_a XOR sig_b, sig_a AND sig_b].  W1 is the only operand worth staging:
+// a block covers 256 pairs x 128 outputs and stages W1[n0 .. n0+127][k0 ..
+// k0+63] in LDS per step, double-buffered (the next step's tile is loaded
+// into registers while this step's MFMAs run), so each W1 byte fetched from
+// L2 feeds 256 pairs.  Each of the 4 waves owns 64 pairs x 128 outputs (2 x 4
+// MFMA tiles of 32 x 32); its pair operands come from one 64-bit signature
+// word per pair and step (fetched a step ahead), expanded 8 bits at a time to
+// BF16 0/1 fragments.  Rows are padded to 144 bytes so the 16-byte fragment
+// reads of 16 consecutive rows hit 16 distinct 4-bank groups.
+// Block order is XCD-aware: the 8 XCDs take blocks round-robin, and XCDs x
+// and x + 4 both work on output quarter x & 3, so each XCD's L2 holds a
+// quarter of W1 (2 MB) instead of all of it.
+// Every output accumulates the same v_mfma_f32_32x32x16_bf16 sequence over k
+// (ascending steps of 16, same fragment layout) as gemm_nt, so the result is
+// bitwise the same as with gemm_nt.
+constexpr int kW1BM = 256, kW1BN = 128, kW1BK = 64, kW1Pad = kW1BK + 8;
+
+__device__ __forceinline__ bf16x8 expand_byte(uint32_t byte) {
+  // bits 2j, 2j+1 -> dword j = {bf16(bit 2j), bf16(bit 2j+1)}: spread bit
+  // 2j+1 to bit 16, then one 24-bit multiply by 0x3F80 (1.0 in BF16)
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 d;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t sb = (byte >> (2 * j)) & 3u;
+    d[j] = __umul24((sb | (sb << 15)) & 0x10001u, 0x3F80u);
+  }
+  return __builtin_bit_cast(bf16x8, d);
+}
+
+template <class EPI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_pairs_w1(const uint64_t* sig, const uint64_t* pairs,
+                                                     const uint16_t* w1b, EPI E, uint32_t M,
+                                                     uint32_t row_blocks) {
+  __shared__ __attribute__((aligned(16))) uint16_t wt[2][kW1BN][kW1Pad];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
+  const uint32_t xcd = blockIdx.x & 7u;
+  const uint32_t rb = (blockIdx.x >> 3) * 2 + (xcd >> 2);
+  if (rb >= row_blocks) return;  // padding blocks (the grid is a multiple of 8)
+  const uint32_t n0 = (xcd & 3u) * kW1BN;
+  const uint32_t m0 = rb * kW1BM + wv * 64;
+  // this lane's two pair rows (tiles i = 0, 1) and their signature rows
+  const uint64_t* sa[2];
+  const uint64_t* sb[2];
+  bool live[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const uint32_t r = m0 + 32 * i + (lane & 31);
+    live[i] = r < M;
+    const uint64_t pr = live[i] ? pairs[r] : 0ull;
+    sa[i] = sig + (pr >> 32) * kSigWords;
+    sb[i] = sig + (pr & 0xFFFFFFFFu) * kSigWords;
+  }
+  // W1 loader: thread t copies row t / 2, k-half t % 2 (4 x 16 bytes) of a step
+  const uint32_t lrow = tid >> 1, lk = (tid & 1) * 32;
+  const uint16_t* wsrc = w1b + (uint64_t)(n0 + lrow) * kIn + lk;
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 stage[4];
+  auto load_w = [&](uint32_t k0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) stage[j] = *reinterpret_cast<const u32x4*>(wsrc + k0 + 8 * j);
+  };
+  auto store_w = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) *reinterpret_cast<u32x4*>(&wt[buf][lrow][lk + 8 * j]) = stage[j];
+  };
+  // the step's pair word: k < 4096 -> XOR of the two signatures, else AND
+  auto pair_word = [&](int i, uint32_t step) -> uint64_t {
+    if (!live[i]) return 0ull;
+    const uint32_t w = step & 63u;
+    const uint64_t a = sa[i][w], b = sb[i][w];
+    return step < 64 ? (a ^ b) : (a & b);
+  };
+  f32x16 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x16{0};
+
+  constexpr uint32_t kSteps = kIn / kW1BK;  // 128
+  load_w(0);
+  store_w(0);
+  uint64_t xw[2] = {pair_word(0, 0), pair_word(1, 0)};
+  __syncthreads();
+  const uint32_t half = 8 * (lane >> 5);
+  for (uint32_t step = 0; step < kSteps; ++step) {
+    const int buf = step & 1;
+    const bool more = step + 1 < kSteps;
+    uint64_t xn[2] = {0ull, 0ull};
+    if (more) {
+      load_w((step + 1) * kW1BK);
+      xn[0] = pair_word(0, step + 1);
+      xn[1] = pair_word(1, step + 1);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      bf16x8 a[2], b[4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = expand_byte((uint32_t)(xw[i] >> (16 * q + half)) & 0xFFu);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        b[j] = *reinterpret_cast<const bf16x8*>(&wt[buf][32 * j + (lane & 31)][16 * q + half]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) {
+      store_w(buf ^ 1);
+      xw[0] = xn[0];
+      xw[1] = xn[1];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const uint32_t m = m0 + 32 * i + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+        const uint32_t n = n0 + 32 * j + (lane & 31);
+        if (m < M) E.store(m, n, acc[i][j][r]);
+      }
+}
+
+template <class EPI>
+hipError_t gemm_w1(const uint64_t* sig, const uint64_t* pairs, const uint16_t* w1b, EPI E,
+                   uint32_t M, hipStream_t s) {
+  const uint32_t row_blocks = (M + kW1BM - 1) / kW1BM;
+  // 4 output quarters per row block; XCDs x and x + 4 take quarter x & 3
+  const uint32_t grid = ((row_blocks + 1) / 2) * 8;
+  hipLaunchKernelGGL((gemm_pairs_w1<EPI>), dim3(grid), dim3(256), 0, s, sig, pairs, w1b, E, M,
+                     row_blocks);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ small ops
 // logit[m] = a2[m] . w3 + b3 (one wave per row, fixed-order reduction).
 __global__ void head_forward(const float* a2, const float* w3, const float* b3, uint32_t M,
@@ -306,9 +447,14 @@ hipError_t mlp_forward(MlpState& S, const uint64_t* sig, const uint64_t* pairs, 
   PairRows X{sig, pairs, M};
   Dense W1{S.w1b, kIn, kH1};
   EpiHidden E1{S.params + kOffB1, S.a1, train ? S.a1t : nullptr, nullptr, kH1, S.max_batch};
-  // layer 1: each expanded pair-row fragment feeds four MFMAs (measured
-  // faster than 2x2 despite one wave per SIMD: 200 vs 181 TFLOP/s)
-  if ((e = gemm<2, 4>(X, W1, E1, M, kH1, kIn, s))) return e;
+  // layer 1: the LDS-staged kernel for batches that fill the chip (64 row
+  // blocks x 4 quarters = one block per CU from 16,384 pairs), else the
+  // direct-load one (training batches of a few hundred pairs)
+  if (M >= 16384) {
+    if ((e = gemm_w1(sig, pairs, S.w1b, E1, M, s))) return e;
+  } else if ((e = gemm(X, W1, E1, M, kH1, kIn, s))) {
+    return e;
+  }
   Dense A1{S.a1, kH1, M};
   Dense W2{S.w2b, kH1, kH2};
   EpiHidden E2{S.params + kOffB2, S.a2b, nullptr, S.a2, kH2, 0};

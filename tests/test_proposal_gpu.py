@@ -142,14 +142,17 @@ def test_mlp_forward_matches_reference(kr):
 
 
 def test_mlp_wide_tiles_match_narrow_and_reference(kr):
-    """A forward of 65,536 pairs in one chunk runs the first layer with 2 x 4 MFMA tiles
-    per wave (the scoring path's chunks); it equals, bit for bit, the same pairs forwarded
-    in chunks of 512 (one tile per wave), and sampled rows match the CPU reference."""
+    """A forward of 65,728 pairs in one chunk runs the first layer on the LDS-staged
+    kernel (256 pairs x 128 outputs per block, 2 x 4 MFMA tiles per wave; 257 row
+    blocks, so the last one is ragged and the grid has a padding block) and the second
+    with 2 x 2 tiles per wave, as the scoring path's chunks do; it equals, bit for bit,
+    the same pairs forwarded in chunks of 512 (one tile per wave), and sampled rows match
+    the CPU reference."""
     import torch
     from oracle import mlp_ref as R
     rng = np.random.default_rng(21)
     sig = rng.integers(0, 2 ** 63, size=(300, 64), dtype=np.uint64)
-    M = 65536
+    M = 65536 + 192
     ij = rng.integers(0, 300, size=(M, 2))
     pairs = (ij[:, 0].astype(np.uint64) << np.uint64(32)) | ij[:, 1].astype(np.uint64)
     d_sig = torch.as_tensor(sig.view(np.int64), device="cuda")
@@ -170,7 +173,7 @@ def test_mlp_wide_tiles_match_narrow_and_reference(kr):
         torch.cuda.synchronize()
         zw, zn = z_w.cpu().numpy(), z_n.cpu().numpy()
         assert (zw.view(np.uint32) == zn.view(np.uint32)).all()
-        rows = rng.choice(M, 96, replace=False)
+        rows = np.concatenate([rng.choice(M, 96, replace=False), np.arange(M - 8, M)])
         ref = R.forward(R.unflatten(p), R.pair_inputs(sig, pairs[rows]))["z"]
         assert _close(zw[rows], ref, 1e-2)
     finally:
