@@ -242,15 +242,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
   if (rb >= row_blocks) return;  // padding blocks (the grid is a multiple of 8)
   const uint32_t n0 = (xcd & 3u) * kW1BN;
   const uint32_t m0 = rb * kW1BM + wv * 64;
-  // this lane's two pair rows (tiles i = 0, 1) and their signature rows
+  // this lane's two pair rows (tiles i = 0, 1) and their signature rows; a row
+  // past M reads signature row 0 and is masked to zero
   const uint64_t* sa[2];
   const uint64_t* sb[2];
-  bool live[2];
+  uint64_t live[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     const uint32_t r = m0 + 32 * i + (lane & 31);
-    live[i] = r < M;
-    const uint64_t pr = live[i] ? pairs[r] : 0ull;
+    live[i] = r < M ? ~0ull : 0ull;
+    const uint64_t pr = r < M ? pairs[r] : 0ull;
     sa[i] = sig + (pr >> 32) * kSigWords;
     sb[i] = sig + (pr & 0xFFFFFFFFu) * kSigWords;
   }
@@ -267,12 +268,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 #pragma unroll
     for (int j = 0; j < 4; ++j) *reinterpret_cast<u32x4*>(&wt[buf][lrow][lk + 8 * j]) = stage[j];
   };
-  // the step's pair word: k < 4096 -> XOR of the two signatures, else AND
-  auto pair_word = [&](int i, uint32_t step) -> uint64_t {
-    if (!live[i]) return 0ull;
-    const uint32_t w = step & 63u;
-    const uint64_t a = sa[i][w], b = sb[i][w];
-    return step < 64 ? (a ^ b) : (a & b);
+  // the step's pair word: k < 4096 -> XOR of the two signatures, else AND.
+  // The raw words are loaded a step ahead and combined only when used, so
+  // no wait for them (or for the W1 loads issued before them) falls inside
+  // the step that issues them.
+  auto combine = [&](int i, uint32_t step, uint64_t a, uint64_t b) -> uint64_t {
+    return (step < 64 ? (a ^ b) : (a & b)) & live[i];
   };
   f32x16 acc[2][4];
 #pragma unroll
@@ -283,18 +284,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
   constexpr uint32_t kSteps = kIn / kW1BK;  // 128
   load_w(0);
   store_w(0);
-  uint64_t xw[2] = {pair_word(0, 0), pair_word(1, 0)};
+  uint64_t xw[2] = {combine(0, 0, sa[0][0], sb[0][0]), combine(1, 0, sa[1][0], sb[1][0])};
   __syncthreads();
   const uint32_t half = 8 * (lane >> 5);
   for (uint32_t step = 0; step < kSteps; ++step) {
     const int buf = step & 1;
     const bool more = step + 1 < kSteps;
-    uint64_t xn[2] = {0ull, 0ull};
+    uint64_t na[2] = {0ull, 0ull}, nb[2] = {0ull, 0ull};
     if (more) {
       load_w((step + 1) * kW1BK);
-      xn[0] = pair_word(0, step + 1);
-      xn[1] = pair_word(1, step + 1);
+      const uint32_t w = (step + 1) & 63u;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        na[i] = sa[i][w];
+        nb[i] = sb[i][w];
+      }
     }
+    // keep the next step's loads ahead of this step's MFMAs (left alone, the
+    // scheduler sinks them next to their use at the end of the step)
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       bf16x8 a[2], b[4];
@@ -309,10 +317,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    // ... and their use after them (the MFMAs of the step issue first)
+    __builtin_amdgcn_sched_barrier(0);
     if (more) {
       store_w(buf ^ 1);
-      xw[0] = xn[0];
-      xw[1] = xn[1];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) xw[i] = combine(i, step + 1, na[i], nb[i]);
     }
     __syncthreads();
   }
