@@ -68,6 +68,30 @@ def recorded_traffic(name="census_fast_n5_traffic.json"):
     return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
 
 
+def provenance():
+    """What produced this record: a hash of the library sources and this script (the GPU
+    copy of the tree has no git metadata), the git revision when there is one, and the
+    master seeds of the seeded inputs."""
+    import glob
+    import hashlib
+    import subprocess
+    from paper_2606_15437_amd import inputs as I
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2606_15437_amd", "csrc", "*")) +
+                   [os.path.join(ROOT, "include", "kripke.h"), os.path.abspath(__file__)])
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(f, "rb").read())
+    try:
+        rev = subprocess.run(["git", "rev-parse", "HEAD"], cwd=ROOT, capture_output=True,
+                             text=True, timeout=10).stdout.strip() or None
+    except (OSError, subprocess.SubprocessError):
+        rev = None
+    seeds = {name: hex(getattr(I, name)) for name in ("SEED_C1", "SEED_C2", "SEED_C3", "SEED_C4",
+                                                       "SEED_C5_TEST", "SEED_C5_TRAIN",
+                                                       "SEED_ADV")}
+    return {"sources_sha256": h.hexdigest(), "git_rev": rev, "seeds": seeds}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -344,6 +368,14 @@ def main():
     from paper_2606_15437_amd import inputs as I
     from paper_2606_15437_amd import kripke as K
 
+    if args.copy_mib:  # reference dispatch for the HBM byte counters
+        torch.cuda.set_device(0)
+        src = torch.ones(args.copy_mib << 18, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     if args.only:
         torch.cuda.set_device(0)
         stream = torch.cuda.current_stream()
@@ -363,13 +395,6 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-
-    if args.copy_mib:
-        src = torch.ones(args.copy_mib << 18, dtype=torch.int32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
 
     calib = K.kripke_calibrate_int32(stream)
     log(f"INT32 VALU calibration: {calib / 1e12:.2f} T lane-ops/s "
@@ -495,6 +520,7 @@ def main():
         "active_synthesis": synthesis,
         "correspondence": correspondence,
         "adversarial": adversarial,
+        "provenance": provenance(),
     }
     print(json.dumps(rec))
 

@@ -103,9 +103,12 @@ class Verifier:
         self.chunk = chunk
         self.evals = 0.0
         self.log = log
-        # wall time and evaluations per stage ("agree n=1", ..., "split n=8")
+        # wall time and evaluations per stage ("agree n=1", ..., "split n=8"), and
+        # for the split stages the executed INT32 lane-operations (Proposition 2's
+        # bit-ops of the compiled biconditionals x models scanned / 32)
         self.stage_s = {}
         self.stage_evals = {}
+        self.stage_ops = {}
         code, offs = I.pack(formulas)
         self.code = np.concatenate([code, np.array([I.IFF], dtype=np.uint8)])
         self.offs = offs[:-1].astype(np.int64)
@@ -137,6 +140,18 @@ class Verifier:
         self.stage_s[name] = self.stage_s.get(name, 0.0) + time.time() - t0
         self.stage_evals[name] = self.stage_evals.get(name, 0.0) + evals
         self.evals += evals
+
+    def _bitops(self, ia, ib, n):
+        """Executed bit-ops per evaluation of each pair's compiled biconditional."""
+        code, offs = self._programs(ia, ib, True)
+        st = K.kripke_program_stats(code, offs, NVARS)
+        return n * st[:, 1].astype(np.float64) + n * n * st[:, 0].astype(np.float64)
+
+    def stage_rates(self):
+        """INT32 lane-operations per second of each split stage (frames up to the
+        separating one, else all; the stage's wall time includes host compilation)."""
+        return {k: self.stage_ops[k] / self.stage_s[k] / 1e12 for k in self.stage_s
+                if self.stage_s[k] > 0 and self.stage_ops.get(k)}
 
     def agree_through(self, ia, ib, nmax=4, layers=None):
         """Mask of pairs whose biconditional has no countermodel on any frame with
@@ -180,6 +195,13 @@ class Verifier:
                 where[sub[k != K.NO_KEY]] = n
             self._stage(f"split n={n}", t0,
                         float(len(idx)) * len(self.panel[n]) * (1 << (NVARS * n)))
+            if len(idx):  # executed work, counted outside the stage's time
+                k = found[idx]
+                scanned = np.where(k != K.NO_KEY,
+                                   (k >> np.uint64(NVARS * n + 4)).astype(np.float64) + 1,
+                                   float(len(self.panel[n])))
+                self.stage_ops[f"split n={n}"] = self.stage_ops.get(f"split n={n}", 0.0) + float(
+                    (self._bitops(ia[idx], ib[idx], n) * scanned).sum()) * (1 << (NVARS * n)) / 32.0
             if self.log:
                 self.log(f"  split n={n}: {len(idx)} in, {int((where == n).sum())} split "
                          f"({self.stage_s[f'split n={n}']:.2f} s)")
@@ -322,6 +344,7 @@ def run(n_test=10000, n_train=10000, universe_pairs=5_500_000, train_pairs=5_500
             f"{prefix}")
     rec["test"]["verify_stages_s"] = dict(ver.stage_s)
     rec["test"]["verify_stage_evals"] = dict(ver.stage_evals)
+    rec["test"]["verify_stage_T_int32_ops_per_s"] = ver.stage_rates()
     # the paper's stricter hit (Section 9): the biconditional also has no countermodel on
     # any frame with five worlds (every labelled frame, every valuation)
     t4 = time.time()
