@@ -158,7 +158,13 @@ def bench_split(args, stream):
             "roofline": {"bound": "alu", "achieved": per["8"]["T_int32_ops_per_s"],
                          "peak": PEAK_INT32 / 1e12, "unit": "T INT32 ops/s",
                          "frac": per["8"]["T_int32_ops_per_s"] / (PEAK_INT32 / 1e12),
-                         "traffic": recorded_traffic("split_list_n8_traffic.json"),
+                         # the counters were taken on a smaller workload than this one:
+                         # reported beside, not as this launch's traffic
+                         "traffic": None,
+                         "traffic_profiled": {
+                             "bytes_per_launch": recorded_traffic("split_list_n8_traffic.json"),
+                             "workload": "2,048 pairs x 262,144 frames at n = 8 "
+                                         "(profiles/split_list_n8.md)"},
                          "kernel": "census_fast<8,2,*,LIST>",
                          "all_n_achieved": tot_ops / tot_ms / 1e9},
             "selection": dict(stats, seconds=sel_s),
