@@ -282,9 +282,10 @@ def bench_synthesis():
 
 
 def bench_correspondence():
-    """Frame-correspondence recovery (Section 10) over the census corpus with two condition
-    libraries: the eight conditions Table 9 names, and our 136-condition library (16 base
-    conditions and every conjunction of two).  Every recovered (formula, condition) is
+    """Frame-correspondence recovery (Section 10) over the census corpus with three condition
+    libraries: the eight conditions Table 9 names; those and coreflexive, shift reflexive and
+    functional frames; and our 136-condition library (16 base conditions and every
+    conjunction of two).  Every recovered (formula, condition) is
     re-confirmed over all 33,554,432 five-world frames."""
     import collections
     from paper_2606_15437_amd import census_corpus as C
@@ -295,6 +296,7 @@ def bench_correspondence():
                      "reconfirmed_on": "all 33,554,432 five-world frames"}}
     maps = None
     for name, lib in (("table9_conditions", R.table9_library()),
+                      ("table9_and_textbook", R.textbook_library()),
                       ("library_136", R.library())):
         t0 = time.time()
         res = R.recover(corpus, max_n=4, log=log, lib=lib)
@@ -359,7 +361,7 @@ def main():
     ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-reproduction", action="store_true")
-    ap.add_argument("--only", choices=("mlp", "split"),
+    ap.add_argument("--only", choices=("mlp", "split", "correspondence"),
                     help="run one secondary leg alone and print its record (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -385,7 +387,12 @@ def main():
     if args.only:
         torch.cuda.set_device(0)
         stream = torch.cuda.current_stream()
-        leg = bench_mlp(stream) if args.only == "mlp" else bench_split(args, stream)
+        if args.only == "mlp":
+            leg = bench_mlp(stream)
+        elif args.only == "split":
+            leg = bench_split(args, stream)
+        else:
+            leg = bench_correspondence()
         leg.pop("_survivors", None)
         print(json.dumps({"only": args.only, args.only: leg}))
         return

@@ -74,12 +74,21 @@ def base_conditions():
                                            for w in W(n) for v in W(n) for u in W(n) if v < u), s),
         "empty": lambda b, n, s: _all((~b(w, v) for w in W(n) for v in W(n)), s),
         "universal": lambda b, n, s: _all((b(w, v) for w in W(n) for v in W(n)), s),
+        "coreflexive": lambda b, n, s: _all((~b(w, v) for w in W(n) for v in W(n) if w != v), s),
     }
+
+
+# The 16 base conditions of our own library (coreflexive frames are the conjunction
+# symmetric & antisymmetric there).
+LIBRARY_BASE = ("reflexive", "irreflexive", "serial", "transitive", "symmetric", "euclidean",
+                "partially functional", "functional", "dense", "directed", "antisymmetric",
+                "asymmetric", "shift reflexive", "connected", "empty", "universal")
 
 
 def library():
     """The base conditions and every conjunction of two of them."""
-    base = base_conditions()
+    all_base = base_conditions()
+    base = {name: all_base[name] for name in LIBRARY_BASE}
     lib = dict(base)
     for (a, fa), (c, fc) in itertools.combinations(base.items(), 2):
         lib[f"{a} & {c}"] = (lambda fa, fc: lambda b, n, s: fa(b, n, s) & fc(b, n, s))(fa, fc)
@@ -95,6 +104,17 @@ def table9_library():
     """Only the eight first-order conditions Table 9 names."""
     base = base_conditions()
     return {name: base[name] for name in TABLE9_CONDITIONS}
+
+
+# Conditions beyond Table 9 whose one-variable modal definitions are standard: coreflexive
+# (p -> []p), shift reflexive ([]([]p -> p)) and functional (<>p <-> []p).
+TEXTBOOK_EXTRA = ("coreflexive", "shift reflexive", "functional")
+
+
+def textbook_library():
+    """Table 9's eight conditions and the three of TEXTBOOK_EXTRA."""
+    base = base_conditions()
+    return {name: base[name] for name in TABLE9_CONDITIONS + TEXTBOOK_EXTRA}
 
 
 def extensions(names, max_n=4, chunk=1 << 20, lib=None):

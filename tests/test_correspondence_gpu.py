@@ -70,6 +70,17 @@ def test_table9_correspondents(cc):
             assert want[name] in rec, (name, rec)
 
 
+def test_textbook_axioms_recover_their_conditions(cc):
+    """The one-variable definitions of the three conditions added to Table 9's: p -> []p
+    (coreflexive), []([]p -> p) (shift reflexive) and <>p <-> []p (functional), over all
+    frames with at most four worlds."""
+    rows = [("coreflexive", "p -> []p"), ("shift reflexive", "[]([]p -> p)"),
+            ("functional", "(<>p -> []p) & ([]p -> <>p)")]
+    got = cc.recover([I.parse(t) for _, t in rows], max_n=4, lib=cc.textbook_library())
+    for (name, _), rec in zip(rows, got):
+        assert rec == [name], (name, rec)
+
+
 def test_recovered_conditions_hold_on_five_worlds(cc):
     """Re-confirmation on five-world frames (Section 10): Val_5 of each Sahlqvist axiom
     of Table 9 equals its condition's extension on every one of the 33,554,432 frames;
@@ -89,9 +100,16 @@ def test_corpus_summary(cc):
     raw = I.enumerate_formulas(7)
     from paper_2606_15437_amd import census_corpus
     _, reps, corpus = census_corpus.build_corpus()
-    for lib in (cc.library(), cc.table9_library()):
+    got = {}
+    for name, lib in (("136", cc.library()), ("table9", cc.table9_library()),
+                      ("textbook", cc.textbook_library())):
         out = cc.recover(corpus, max_n=4, lib=lib)
         trivial = sum(1 for o in out if o == "trivial")
         recovered = sum(1 for o in out if isinstance(o, list) and o)
         assert len(out) == 5624 and recovered > 0 and len(raw) == 44678
         assert trivial == 2798
+        got[name] = out
+    # a larger library recovers a superset: every Table-9 match keeps its condition
+    for a, b in zip(got["table9"], got["textbook"]):
+        if isinstance(a, list) and a:
+            assert set(a) <= set(b)

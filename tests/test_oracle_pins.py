@@ -236,6 +236,29 @@ def test_table9_correspondences(orc):
             assert all(v == conds[cond] for v, conds in ext), name
 
 
+def test_textbook_correspondences(orc):
+    """Three standard correspondences beyond Table 9, on every frame with n <= 3:
+    p -> []p holds exactly where R is contained in the identity, []([]p -> p) exactly where
+    every world with a predecessor sees itself, <>p <-> []p exactly where every world has
+    one successor."""
+    def coreflexive(R, n):
+        return all(not R[w][v] for w in range(n) for v in range(n) if w != v)
+
+    def shift_reflexive(R, n):
+        return all(R[v][v] for w in range(n) for v in range(n) if R[w][v])
+
+    def functional(R, n):
+        return all(sum(R[w]) == 1 for w in range(n))
+
+    for text, cond in (("p -> []p", coreflexive), ("[]([]p -> p)", shift_reflexive),
+                       ("(<>p -> []p) & ([]p -> <>p)", functional)):
+        code = I.parse(text)
+        for n in (1, 2, 3):
+            for f in range(1 << (n * n)):
+                R = [[(f >> (w * n + v)) & 1 for v in range(n)] for w in range(n)]
+                assert frame_valid(orc, code, f, n) == cond(R, n), (text, n, f)
+
+
 # ------------------------------------------------------------------ P2
 def test_prop6_certificate(orc):
     g = dict(ln.split(":", 1) for ln in _golden_lines("prop6_certificate.txt"))
