@@ -540,6 +540,133 @@ __device__ __forceinline__ uint64_t candidate(const Ctx<N, NV, LS, MODE>& c, int
   return readlane64(lk, fl);
 }
 
+// Words of one staged program (the micro-ops, 8-byte padded, and slack).
+constexpr int kProgWords = kMaxMicro / 4 + 4;
+
+// One work item of mode 3: a range of two-frame blocks for a group of up to
+// kListGroupMax formulas (consecutive in the launch order), first keys only.
+// The group's programs are staged side by side in the wave's LDS area; each
+// block's two frames are loaded and decoded once, then every formula of the
+// group without a key is interpreted on them.  A formula's first failing
+// block holds its least key in the range (blocks run in increasing position
+// order); the key goes out at once and the formula leaves the group.
+template <int N, int NV, int LS>
+__device__ __forceinline__ void list2_item(const FastArgs& a, Ctx<N, NV, LS, 3>& c,
+                                           uint32_t (*progs)[kProgWords], uint32_t* pws,
+                                           uint64_t item, int lane, uint64_t rag_lo,
+                                           uint64_t rag_hi) {
+  using G = Geo<N, NV, LS, 3>;
+  static_assert(G::CHB == 0, "a two-frame block holds all valuations of its frames");
+  const uint32_t lane_pos = (uint32_t)(lane >> G::LV);
+  const uint64_t blk_end = a.blk_begin + a.nblk;
+  const uint32_t f0 = (uint32_t)(item / a.items_per_formula) * a.group;
+  const uint32_t ng = a.nformulas - f0 < a.group ? a.nformulas - f0 : a.group;
+  const uint64_t b0 = a.blk_begin + (item % a.items_per_formula) * a.blocks_per_item;
+  const uint64_t b1 = b0 + a.blocks_per_item < blk_end ? b0 + a.blocks_per_item : blk_end;
+  const uint64_t p0 = (b0 << G::B) > a.pos_begin ? (b0 << G::B) : a.pos_begin;
+
+  // stage the group's programs; a formula whose known key precedes the range,
+  // or whose program is TOP (no countermodel), takes no part
+  uint32_t live = 0, bot = 0;
+  for (uint32_t j = 0; j < ng; ++j) {
+    const uint32_t f = a.order[f0 + j];
+    uint64_t known = __hip_atomic_load(a.out_key + (uint64_t)f * a.out_stride, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+    known = readlane64(known, 0);
+    if (known != ~0ull && (known >> (G::V + 4)) < p0) continue;
+    const uint32_t q0 = a.uoff[f] >> 2, pw = (a.uoff[f + 1] >> 2) - q0;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.ucode) + q0;
+    for (uint32_t i = lane; i < pw; i += 64) progs[j][i] = src[i];
+    const uint64_t first = ((uint64_t)__builtin_amdgcn_readfirstlane(src[1]) << 32) |
+                           __builtin_amdgcn_readfirstlane(src[0]);
+    if (first == (uint64_t)(U_LOAD + L_TOP)) continue;
+    if (first == (uint64_t)(U_LOAD + L_BOT)) bot |= 1u << j;
+    if (lane == 0) pws[j] = pw;
+    live |= 1u << j;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+  for (uint64_t blk = b0; blk < b1 && live; ++blk) {
+    // each half-wave's frame (position blk << B | lane_pos; a position past
+    // the list end, in a ragged last block, loads the last frame and is masked
+    // out of the failure test) as per-lane relation words, one signed
+    // bit-field extract per word from the lane's successor rows
+    const uint64_t pbase = blk << G::B;
+    {
+      uint64_t fp = pbase | lane_pos;
+      if (fp >= a.pos_end) fp = a.pos_end - 1;
+      const uint32_t* r = a.list_succ + fp * N;
+      uint32_t row[N];
+#pragma unroll
+      for (int w = 0; w < N; ++w) row[w] = r[w];
+#pragma unroll
+      for (int w = 0; w < N; ++w)
+#pragma unroll
+        for (int v = 0; v < N; ++v) {
+          uint32_t x;
+          asm volatile("v_bfe_i32 %0, %1, %2, 1" : "=v"(x) : "v"(row[w]), "i"(v));
+          c.ru[w][v] = x;
+        }
+    }
+    bool in_range = true;
+    if (blk == rag_lo || blk == rag_hi) {
+      const uint64_t pos = pbase | lane_pos;
+      in_range = pos >= a.pos_begin && pos < a.pos_end;
+    }
+    for (uint32_t j = 0; j < ng; ++j) {
+      if (!((live >> j) & 1u)) continue;
+      if ((bot >> j) & 1u) {
+        // BOT is false everywhere: a zero accumulator, no interpretation
+#pragma unroll
+        for (int s = 0; s < G::S; ++s)
+#pragma unroll
+          for (int w = 0; w < N; ++w) c.acc[s][w] = 0u;
+      } else {
+        const uint32_t* prog = progs[j];
+        const uint64_t first = ((uint64_t)__builtin_amdgcn_readfirstlane(prog[1]) << 32) |
+                               __builtin_amdgcn_readfirstlane(prog[0]);
+        run<N, NV, LS, 3>(c, prog, first, (uint32_t)__builtin_amdgcn_readfirstlane(pws[j]) >> 1);
+      }
+      // failing (valuation) bits of set s on this lane
+      auto fail_of = [&](int s) {
+        uint32_t all = ~0u;
+#pragma unroll
+        for (int w = 0; w < N; ++w) all &= c.acc[s][w];
+        return in_range ? ~all : 0u;
+      };
+      uint32_t anyfail = 0;
+#pragma unroll
+      for (int s = 0; s < G::S; ++s) anyfail |= fail_of(s);
+      if (!__ballot(anyfail != 0)) continue;
+      // the first half-wave's frame precedes every valuation of the second:
+      // the sets are searched on its lanes first, then on the whole wave
+      uint64_t best = ~0ull;
+      bool found = false;
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const uint64_t lanes = half == 0 ? 0xFFFFFFFFull : ~0ull;
+#pragma unroll
+        for (int s = 0; s < G::S; ++s) {
+          if (!found) {
+            const uint32_t fail = fail_of(s);
+            const uint64_t bal = __ballot(fail != 0) & lanes;
+            if (bal) {
+              const uint64_t k = candidate(c, s, fail, bal, blk, 0u, lane);
+              best = k < best ? k : best;
+              found = true;
+            }
+          }
+        }
+      }
+      if (lane == 0)
+        atomicMin(a.out_key + (uint64_t)a.order[f0 + j] * a.out_stride, (unsigned long long)best);
+      live = (uint32_t)__builtin_amdgcn_readfirstlane((int)(live & ~(1u << j)));
+    }
+  }
+}
+
 template <int N, int NV, int LS, int MODE, bool FUSED>
 // The eight-set and list variants are sized for four waves per SIMD.
 __global__ __launch_bounds__(256)
@@ -549,14 +676,16 @@ void census_fast(FastArgs a) {
   static_assert(G::V >= 5, "fast kernel needs n * nvars >= 5");
   static_assert(!G::LIST || (G::V >= 5 + G::LV + LS && !FUSED),
                 "list mode needs the lane and set bits to be valuation bits");
-  __shared__ uint32_t sprog[4][kMaxMicro / 4 + 4];
+  // staged programs: one per wave, a group of them in mode 3
+  __shared__ uint32_t sprog[4][G::LIST2 ? kListGroupMax : 1][kProgWords];
+  __shared__ uint32_t spw[4][G::LIST2 ? kListGroupMax : 1];
   __shared__ uint32_t sspill[4][G::LDS_WORDS > 0 ? G::LDS_WORDS * 64 : 1];
   // fused mode: per-lane failure counts of the classes T, S4, S5, private to
   // the lane (only blocks that can hold a reflexive frame touch them, so they
   // need not occupy registers through the interpreter)
   __shared__ uint32_t scls[4][FUSED ? 3 : 1][64];
   const int lane = threadIdx.x & 63;
-  uint32_t* prog = sprog[threadIdx.x >> 6];
+  uint32_t* prog = sprog[threadIdx.x >> 6][0];
   constexpr int NC = FUSED ? 4 : 1;
   const uint64_t blk_end = a.blk_begin + a.nblk;
 
@@ -587,6 +716,12 @@ void census_fast(FastArgs a) {
     if (lane == 0) item = atomicAdd(a.queue, 1ull);
     item = readlane64(item, 0);
     if (item >= a.total_items) break;
+    if constexpr (G::LIST2) {
+      list2_item<N, NV, LS>(a, c, sprog[threadIdx.x >> 6], spw[threadIdx.x >> 6], item, lane,
+                            rag_lo, rag_hi);
+      continue;
+    }
+    // (mode 3 items never reach this point)
     const uint32_t f = a.order[item / a.items_per_formula];
     const uint64_t b0 = a.blk_begin + (item % a.items_per_formula) * a.blocks_per_item;
     const uint64_t b1 = b0 + a.blocks_per_item < blk_end ? b0 + a.blocks_per_item : blk_end;
@@ -634,26 +769,7 @@ void census_fast(FastArgs a) {
     for (uint64_t blk = b0; blk < b1 && !done; ++blk) {
       const uint64_t pbase = blk << G::B;
       uint64_t base = 0;
-      if constexpr (G::LIST2) {
-        // each half-wave's frame (position pbase | lane_pos; a position past the
-        // list end, in a ragged last block, loads the last frame and is masked
-        // out of the failure test) as per-lane relation words, one signed
-        // bit-field extract per word from the lane's successor rows
-        uint64_t fp = pbase | lane_pos;
-        if (fp >= a.pos_end) fp = a.pos_end - 1;
-        const uint32_t* r = a.list_succ + fp * N;
-        uint32_t row[N];
-#pragma unroll
-        for (int w = 0; w < N; ++w) row[w] = r[w];
-#pragma unroll
-        for (int w = 0; w < N; ++w)
-#pragma unroll
-          for (int v = 0; v < N; ++v) {
-            uint32_t x;
-            asm volatile("v_bfe_i32 %0, %1, %2, 1" : "=v"(x) : "v"(row[w]), "i"(v));
-            c.ru[w][v] = x;
-          }
-      } else if constexpr (G::LIST) {
+      if constexpr (G::LIST) {
         // the list frame's successor rows, wave-uniform
         // the list is read-only for the kernel's lifetime: reading it through
         // the constant address space gives scalar loads straight into SGPRs
@@ -669,7 +785,7 @@ void census_fast(FastArgs a) {
       // the relation bits in vector registers, expanded there by one signed
       // bit-field extract per word (opaque, so the words stay vector values)
       uint32_t vbase[2] = {0u, 0u};
-      if constexpr (G::RUV && !G::LIST2) {
+      if constexpr (G::RUV) {
         asm volatile("v_mov_b32 %0, %1" : "=v"(vbase[0]) : "s"((uint32_t)base));
         if constexpr (N * G::RV_ROWS > 32)
           asm volatile("v_mov_b32 %0, %1" : "=v"(vbase[1]) : "s"((uint32_t)(base >> 32)));
@@ -679,7 +795,7 @@ void census_fast(FastArgs a) {
 #pragma unroll
         for (int v = 0; v < N; ++v) {
           const int p = w * N + v;
-          if (G::LIST2 || role<N, MODE, G::LF, LS>(p) != R_UNIFORM) continue;
+          if (role<N, MODE, G::LF, LS>(p) != R_UNIFORM) continue;
           if (w < G::RV_ROWS) {
             uint32_t r;
             asm volatile("v_bfe_i32 %0, %1, %2, 1" : "=v"(r) : "v"(vbase[p >> 5]), "i"(p & 31));
@@ -691,7 +807,7 @@ void census_fast(FastArgs a) {
           }
         }
       // valid (lane, set) pairs: positions inside [pos_begin, pos_end)
-      const bool ragged = (!G::LIST || G::LIST2) && (blk == rag_lo || blk == rag_hi);
+      const bool ragged = !G::LIST && (blk == rag_lo || blk == rag_hi);
       // class levels of the block's frames; consumed only after evaluation,
       // so the scalar load overlaps the interpreter
       uint32_t lvl_raw = 0;
@@ -780,35 +896,26 @@ void census_fast(FastArgs a) {
         }
         // one ballot per block while no key is known; then the least key lies in
         // the first failing set (sets follow frame positions, or, in list mode,
-        // valuation bits above the lane bits).  With two list frames per block
-        // the first half-wave's frame comes first whatever its set, so the sets
-        // are searched on its lanes first, then on the whole wave.
+        // valuation bits above the lane bits)
         if (key[0] == ~0ull && __ballot(anyfail != 0)) {
           bool found = false;
 #pragma unroll
-          for (int half = 0; half < (G::LIST2 ? 2 : 1); ++half) {
-            const uint64_t lanes = G::LIST2 && half == 0 ? 0xFFFFFFFFull : ~0ull;
-#pragma unroll
-            for (int s = 0; s < G::S; ++s) {
-              if (!found) {
-                const uint32_t fail = fail_of(s);
-                const uint64_t bal = __ballot(fail != 0) & lanes;
-                if (bal) {
-                  const uint64_t k = candidate(c, s, fail, bal, blk, chunk, lane);
-                  best[0] = k < best[0] ? k : best[0];
-                  found = true;
-                }
+          for (int s = 0; s < G::S; ++s) {
+            if (!found) {
+              const uint32_t fail = fail_of(s);
+              const uint64_t bal = __ballot(fail != 0);
+              if (bal) {
+                const uint64_t k = candidate(c, s, fail, bal, blk, chunk, lane);
+                best[0] = k < best[0] ? k : best[0];
+                found = true;
               }
             }
           }
         }
         // list mode: chunks run in increasing valuation order inside one
         // frame, so the first chunk with a failure holds the frame's least key
-        // (with two frames per block, only if that failure is in the first)
         if constexpr (G::LIST)
-          if (a.decide && best[0] != ~0ull &&
-              (!G::LIST2 || (best[0] >> (G::V + 4)) == pbase))
-            break;
+          if (a.decide && best[0] != ~0ull) break;
       }
 #pragma unroll
       for (int k = 0; k < NC; ++k)

@@ -442,6 +442,16 @@ int enqueue_fast(DeviceState* ds, const DeviceBatch& db, int n, int nvars, int l
   // keys of consecutive formulas (2 for census results, 1 for split keys);
   // list_succ: the frame list of modes 2 and 3
   if (row_formulas == 0) row_formulas = nformulas;
+  // mode 3 scans groups of formulas per work item and searches first keys only
+  uint32_t group = 1;
+  if (mode == 3) {
+    if (!decide || cnt || valid_bits)
+      return fail(KRIPKE_EINTERNAL, "two-frame list blocks search first keys only");
+    group = kListGroupMax;
+    if (const char* env = getenv("KRIPKE_LIST_GROUP"))
+      group = (uint32_t)std::min<long>(kListGroupMax, std::max<long>(1, atol(env)));
+  }
+  const uint64_t ngroups = ((uint64_t)nformulas + group - 1) / group;
   FastArgs a{};
   a.ucode = db.ucode;
   a.uoff = db.uoff;
@@ -454,12 +464,13 @@ int enqueue_fast(DeviceState* ds, const DeviceBatch& db, int n, int nvars, int l
   a.nblk = p1 > p0 ? ((p1 + (1ull << B) - 1) >> B) - a.blk_begin : 0;
   const int per_cu = fast_blocks_per_cu(n, nvars, ls, mode, fused);
   const uint64_t waves = (uint64_t)ds->cus * per_cu * 4;
-  const uint64_t target = std::max<uint64_t>((uint64_t)items_per_wave * waves, nformulas);
-  uint64_t bpi = std::max<uint64_t>(1, (a.nblk * nformulas + target - 1) / target);
+  const uint64_t target = std::max<uint64_t>((uint64_t)items_per_wave * waves, ngroups);
+  uint64_t bpi = std::max<uint64_t>(1, (a.nblk * ngroups + target - 1) / target);
   bpi = std::min<uint64_t>(bpi, 1ull << 16);
   a.blocks_per_item = bpi;
-  a.items_per_formula = (a.nblk + bpi - 1) / bpi;
-  a.total_items = a.items_per_formula * nformulas;
+  a.items_per_formula = (a.nblk + bpi - 1) / bpi;  // per group in mode 3
+  a.total_items = a.items_per_formula * ngroups;
+  a.group = group;
   a.queue = queue;
   a.out_key = key;
   a.out_cnt = cnt;

@@ -68,3 +68,22 @@ def test_two_frame_blocks_match_the_oracle(kr, nframes):
     for i, w in zip(check, want):
         assert int(got[i]) == w, (i, I.to_text(pairs[i][0]), I.to_text(pairs[i][1]))
     assert len(sep) >= 5  # the sample holds separated pairs, not only agreeing ones
+
+
+@pytest.mark.parametrize("nframes", [3, 999, 4096])
+def test_formula_groups_match_single_formulas(kr, monkeypatch, nframes):
+    """A work item of the two-frame kernel scans a group of formulas on each decoded
+    block; every group size gives the keys of one formula per item, with groups cut
+    short at the end of the batch and constant programs (TOP never fails, BOT fails
+    at the first model) inside groups."""
+    p = I.parse("p")
+    pairs = _pairs() + [([I.TOP], [I.BOT]), (p, p), ([I.BOT], [I.BOT]), (p, [I.TOP]),
+                        ([I.TOP], [I.TOP])]
+    frames = I.frame_family(6, nframes)
+    monkeypatch.setenv("KRIPKE_LIST_GROUP", "1")
+    single = kr.split(pairs, frames, 6)
+    assert single[len(pairs) - 5] == 0  # TOP <-> BOT fails at the first model
+    assert single[len(pairs) - 1] == kr.NO_KEY
+    for g in ("2", "3", "4"):
+        monkeypatch.setenv("KRIPKE_LIST_GROUP", g)
+        assert np.array_equal(kr.split(pairs, frames, 6), single), (g, nframes)
