@@ -84,15 +84,16 @@ __host__ __device__ constexpr int role_idx(int p, int LF) {
 }
 
 // List-mode relation rows held in vector registers, per variant: as many as
-// fit four waves per SIMD (at most 128 VGPRs).  At n = 8 with four sets the
-// kernel also keeps two sets of its register stack slot in LDS and has no
-// whole LDS slot, which buys two more rows (measured on the split search:
-// 483 ms with three rows and an LDS slot, 459 ms with five).
+// fit four waves per SIMD (at most 128 VGPRs).  At n = 7 and 8 with four sets
+// the kernel also keeps two sets of its register stack slot in LDS and has no
+// whole LDS slot, which buys more rows (measured on the split search: at
+// n = 8, 483 ms with three rows and an LDS slot, 459 ms with five; at n = 7,
+// 468 ms with one row, two register slots and an LDS slot, 410 ms with six).
 __host__ __device__ constexpr int list_rows(int n, int ls) {
-  return n == 6 ? 6 : n == 7 ? (ls == 0 ? 7 : ls == 1 ? 6 : 1) : (ls == 0 ? 6 : ls == 1 ? 5 : 5);
+  return n == 6 ? 6 : n == 7 ? (ls == 0 ? 7 : 6) : (ls == 0 ? 6 : 5);
 }
-__host__ __device__ constexpr bool list_n8_four_sets(bool list, int n, int ls) {
-  return list && n >= 8 && ls == 2;
+__host__ __device__ constexpr bool list_four_sets(bool list, int n, int ls) {
+  return list && n >= 7 && ls == 2;
 }
 
 template <int N, int NV, int LS, int MODE>
@@ -109,14 +110,15 @@ struct Geo {
   static constexpr int SV = LIST ? LS : 0;                       // set bits that are valuation bits
   static constexpr int B = LIST2 ? 1 : LIST ? 0 : LF + LS;       // log2 frames per block
   static constexpr int CHB = V > 5 + LV + SV ? V - 5 - LV - SV : 0;  // valuation chunk bits
-  // stack slots in registers (one at the eight-world four-set list variant)
+  // stack slots in registers (one at the seven- and eight-world four-set list
+  // variants)
   static constexpr int DS =
-      LS == 0 ? 4 : (LS <= 2 && !list_n8_four_sets(LIST, N, LS) && !LIST2) ? 2 : 1;
+      LS == 0 ? 4 : (LS <= 2 && !list_four_sets(LIST, N, LS) && !LIST2) ? 2 : 1;
   // + slots held wholly in LDS; none at LS = 3 (40 KB per block would cap
-  // residency at three blocks per CU) nor in the eight-world four-set list
-  // variant (its LDS stack sets already take 16 KB per block): programs
-  // needing more slots run in a narrower tier
-  static constexpr int LDS_SLOTS = LS >= 3 || list_n8_four_sets(LIST, N, LS) ? 0 : 1;
+  // residency at three blocks per CU) nor in the seven- and eight-world
+  // four-set list variants (their LDS stack sets already take 14-16 KB per
+  // block): programs needing more slots run in a narrower tier
+  static constexpr int LDS_SLOTS = LS >= 3 || list_four_sets(LIST, N, LS) ? 0 : 1;
   // Block-uniform relation words held in vector registers, by rows of the
   // relation: on gfx950 a VALU instruction with a scalar operand issues at
   // half the rate of one with vector operands only, and the modal terms are
@@ -127,9 +129,9 @@ struct Geo {
   static constexpr int WPE = LS >= 3 || LIST ? 4 : 1;
   // sets of each register stack slot that live in registers; the others sit
   // in the wave's LDS area (this keeps the eight-set census variant and the
-  // eight-world four-set list variant within 128 VGPRs with their relation
-  // rows in registers)
-  static constexpr int SR = (RUV && LS >= 3) || list_n8_four_sets(LIST, N, LS) ? S - 2 : S;
+  // seven- and eight-world four-set list variants within 128 VGPRs with
+  // their relation rows in registers)
+  static constexpr int SR = (RUV && LS >= 3) || list_four_sets(LIST, N, LS) ? S - 2 : S;
   // LDS words per lane: the LDS slots, then the register slots' LDS sets
   static constexpr int LDS_WORDS = (LDS_SLOTS * S + DS * (S - SR)) * N;
 };

@@ -219,15 +219,16 @@ hipError_t gemm(LA A, LB B, EPI E, uint32_t M, uint32_t N, uint32_t K, hipStream
 constexpr int kW1BM = 256, kW1BN = 128, kW1BK = 64, kW1Pad = kW1BK + 8;
 
 __device__ __forceinline__ bf16x8 expand_byte(uint32_t byte) {
-  // bits 2j, 2j+1 -> dword j = {bf16(bit 2j), bf16(bit 2j+1)}: spread bit
-  // 2j+1 to bit 16, then one 24-bit multiply by 0x3F80 (1.0 in BF16)
+  // bits 2j, 2j+1 -> dword j = {bf16(bit 2j), bf16(bit 2j+1)}.  t = byte +
+  // (byte << 15) holds bit 2j at 2j and bit 2j+1 at 16 + 2j; masking those
+  // two and one 24-bit multiply by 0x3F80 >> 2j (1.0 in BF16, whose low
+  // seven bits are zero, so the shift is exact) moves them to bits 0 and 16
+  // as BF16 values: two instructions per dword.
   typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  const uint32_t t = __umul24(byte, 0x8001u);
   u32x4 d;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const uint32_t sb = (byte >> (2 * j)) & 3u;
-    d[j] = __umul24((sb | (sb << 15)) & 0x10001u, 0x3F80u);
-  }
+  for (int j = 0; j < 4; ++j) d[j] = __umul24(t & (0x10001u << (2 * j)), 0x3F80u >> (2 * j));
   return __builtin_bit_cast(bf16x8, d);
 }
 
