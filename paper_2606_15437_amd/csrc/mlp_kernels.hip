@@ -198,6 +198,86 @@ hipError_t gemm(LA A, LB B, EPI E, uint32_t M, uint32_t N, uint32_t K, hipStream
   return gemm_tiles<1, 1>(A, B, E, M, N, K, s);
 }
 
+// ------------------------------------------- scoring: layer 2 and head
+// Scoring forward of layers 2 and 3 without storing layer 2's activations:
+// each MFMA tile covers 32 outputs of 32 rows, and the lanes l with the same
+// l / 32 hold the same rows (lane l % 32 one output each), so a butterfly over
+// l % 32 reduces relu(acc + b2) * w3 of a row over the tile's 32 outputs in a
+// fixed order; lane 0 of each half-wave writes that partial for its rows:
+// part[m][g] = sum over outputs n = 32 g .. 32 g + 31.  The tile of an output
+// group is the same whatever tiles per wave the grid uses, so the partials,
+// and head_sum's logits, do not depend on the tiling.
+constexpr int kHeadGroups = kH2 / 32;  // 32-output groups of layer 2
+
+template <int TM, int TN>
+__global__ __launch_bounds__(256) void gemm_l2_head(Dense A, Dense B, const float* b2,
+                                                     const float* w3, float* part, uint32_t M) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint32_t m0 = blockIdx.x * (64 * TM) + (wv & 1) * (32 * TM);
+  const uint32_t n0 = blockIdx.y * (64 * TN) + (wv >> 1) * (32 * TN);
+  const uint32_t kh = 8 * (lane >> 5);
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x16{0};
+  for (uint32_t k0 = 0; k0 < kH1; k0 += 16) {
+    bf16x8 a[TM], b[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) a[i] = A.load(m0 + 32 * i + (lane & 31), k0 + kh);
+#pragma unroll
+    for (int j = 0; j < TN; ++j) b[j] = B.load(n0 + 32 * j + (lane & 31), k0 + kh);
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const uint32_t n = n0 + 32 * j + (lane & 31);
+    const float bn = b2[n], wn = w3[n];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        float v = fmaxf(acc[i][j][r] + bn, 0.0f) * wn;
+#pragma unroll
+        for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        const uint32_t m = m0 + 32 * i + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+        if ((lane & 31) == 0 && m < M) part[(uint64_t)m * kHeadGroups + (n0 + 32 * j) / 32] = v;
+      }
+  }
+}
+
+// logit[m] = b3 + the row's output-group partials, summed in group order.
+__global__ void head_sum(const float* part, const float* b3, uint32_t M, float* logit) {
+  const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  float s = 0.0f;
+#pragma unroll
+  for (int g = 0; g < kHeadGroups; ++g) s += part[(uint64_t)m * kHeadGroups + g];
+  logit[m] = s + b3[0];
+}
+
+template <int TM, int TN>
+hipError_t l2_head_tiles(Dense A, Dense B, const float* b2, const float* w3, float* part,
+                         uint32_t M, hipStream_t s) {
+  dim3 grid((M + 64 * TM - 1) / (64 * TM), kH2 / (64 * TN));
+  hipLaunchKernelGGL((gemm_l2_head<TM, TN>), grid, dim3(256), 0, s, A, B, b2, w3, part, M);
+  return hipGetLastError();
+}
+
+// The same tile choice as gemm(): 2 x 2 tiles per wave while the grid keeps
+// at least 1,024 blocks, else one.
+hipError_t l2_head(Dense A, Dense B, const float* b2, const float* w3, float* part, uint32_t M,
+                   hipStream_t s) {
+  if (M == 0) return hipSuccess;
+  const uint64_t wide = (uint64_t)((M + 127) / 128) * (kH2 / 128);
+  return wide >= 1024 ? l2_head_tiles<2, 2>(A, B, b2, w3, part, M, s)
+                      : l2_head_tiles<1, 1>(A, B, b2, w3, part, M, s);
+}
+
 // ------------------------------------------------------ layer-1 forward
 // C[m][n] = sum_k x_m(k) W1[n][k] for the scoring and training forwards of
 // large batches: M pairs x 512 outputs x K = 8,192, where x_m(k) is bit k of
@@ -468,6 +548,14 @@ hipError_t mlp_forward(MlpState& S, const uint64_t* sig, const uint64_t* pairs, 
   }
   Dense A1{S.a1, kH1, M};
   Dense W2{S.w2b, kH1, kH2};
+  if (!train) {
+    // scoring: layer 2 reduced against the head in its epilogue; the
+    // per-group partials use the fp32 layer-2 buffer (needed only in training)
+    if ((e = l2_head(A1, W2, S.params + kOffB2, S.params + kOffW3, S.a2, M, s))) return e;
+    hipLaunchKernelGGL(head_sum, dim3(blocks(M)), dim3(256), 0, s, S.a2, S.params + kOffB3, M,
+                       logit);
+    return hipGetLastError();
+  }
   EpiHidden E2{S.params + kOffB2, S.a2b, nullptr, S.a2, kH2, 0};
   if ((e = gemm(A1, W2, E2, M, kH2, kH1, s))) return e;
   hipLaunchKernelGGL(head_forward, dim3(blocks(M, 4)), dim3(256), 0, s, S.a2,
