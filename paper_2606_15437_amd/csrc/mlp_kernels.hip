@@ -213,25 +213,55 @@ template <int TM, int TN>
 __global__ __launch_bounds__(256) void gemm_l2_head(Dense A, Dense B, const float* b2,
                                                      const float* w3, float* part, uint32_t M) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const uint32_t m0 = blockIdx.x * (64 * TM) + (wv & 1) * (32 * TM);
-  const uint32_t n0 = blockIdx.y * (64 * TN) + (wv >> 1) * (32 * TN);
+  // XCD-aware order: the column blocks of one row block run back to back on
+  // the same XCD (blocks are dealt to the 8 XCDs round-robin), so the row
+  // block's activations come from HBM once and from that XCD's L2 after
+  constexpr uint32_t CB = kH2 / (64 * TN);
+  const uint32_t xcd = blockIdx.x & 7u, q = blockIdx.x >> 3;
+  const uint32_t rb = (q / CB) * 8 + xcd, cb = q % CB;
+  const uint32_t m0 = rb * (64 * TM) + (wv & 1) * (32 * TM);
+  const uint32_t n0 = cb * (64 * TN) + (wv >> 1) * (32 * TN);
   const uint32_t kh = 8 * (lane >> 5);
   f32x16 acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = f32x16{0};
-  for (uint32_t k0 = 0; k0 < kH1; k0 += 16) {
-    bf16x8 a[TM], b[TN];
+  // steps of 64 k (four MFMA k-slices); the next step's fragments are loaded
+  // into registers while this step's MFMAs run
+  constexpr uint32_t kStep = 64;
+  bf16x8 xa[4][TM], xb[4][TN], ya[4][TM], yb[4][TN];
+  auto fetch = [&](bf16x8 (&fa)[4][TM], bf16x8 (&fb)[4][TN], uint32_t k0) {
 #pragma unroll
-    for (int i = 0; i < TM; ++i) a[i] = A.load(m0 + 32 * i + (lane & 31), k0 + kh);
+    for (int q = 0; q < 4; ++q) {
 #pragma unroll
-    for (int j = 0; j < TN; ++j) b[j] = B.load(n0 + 32 * j + (lane & 31), k0 + kh);
+      for (int i = 0; i < TM; ++i) fa[q][i] = A.load(m0 + 32 * i + (lane & 31), k0 + 16 * q + kh);
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+      for (int j = 0; j < TN; ++j) fb[q][j] = B.load(n0 + 32 * j + (lane & 31), k0 + 16 * q + kh);
+    }
+  };
+  fetch(xa, xb, 0);
+  for (uint32_t k0 = 0; k0 < kH1; k0 += kStep) {
+    const bool more = k0 + kStep < kH1;
+    if (more) fetch(ya, yb, k0 + kStep);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int j = 0; j < TN; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[q][i], xb[q][j], acc[i][j], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i) xa[q][i] = ya[q][i];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) xb[q][j] = yb[q][j];
+      }
+    }
   }
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
@@ -263,8 +293,11 @@ __global__ void head_sum(const float* part, const float* b3, uint32_t M, float* 
 template <int TM, int TN>
 hipError_t l2_head_tiles(Dense A, Dense B, const float* b2, const float* w3, float* part,
                          uint32_t M, hipStream_t s) {
-  dim3 grid((M + 64 * TM - 1) / (64 * TM), kH2 / (64 * TN));
-  hipLaunchKernelGGL((gemm_l2_head<TM, TN>), grid, dim3(256), 0, s, A, B, b2, w3, part, M);
+  // row blocks padded to a multiple of 8 (the padding blocks' rows are past M:
+  // zero operands, nothing stored)
+  const uint32_t rbs = ((M + 64 * TM - 1) / (64 * TM) + 7) / 8 * 8;
+  const uint32_t grid = rbs * (kH2 / (64 * TN));
+  hipLaunchKernelGGL((gemm_l2_head<TM, TN>), dim3(grid), dim3(256), 0, s, A, B, b2, w3, part, M);
   return hipGetLastError();
 }
 
