@@ -849,7 +849,16 @@ void census_fast(FastArgs a) {
         // the common block (no range edge, no frame of a narrower class, no
         // validity map) tests its uniform conditions once, not per set
         const bool plain = !ragged && !classy && !(kMaps && a.valid_bits);
-        if (plain) {
+        if (plain && key[0] != ~0ull) {
+          // the item's least key is known: failures are only counted
+#pragma unroll
+          for (int s = 0; s < G::S; ++s) {
+            uint32_t all = ~0u;
+#pragma unroll
+            for (int w = 0; w < N; ++w) all &= c.acc[s][w];
+            cnt0 += __builtin_popcount(~all);
+          }
+        } else if (plain) {
 #pragma unroll
           for (int s = 0; s < G::S; ++s) {
             uint32_t all = ~0u;
