@@ -158,12 +158,12 @@ int kripke_frame_validity(const uint8_t *code, const uint32_t *offsets, uint32_t
  * position + nvars*n + 4 <= 64); otherwise KRIPKE_ELIMIT.  Frames of 11 or
  * more worlds (and of 9 or 10 worlds with two or more variables) run on a
  * per-lane world-mask kernel, the others on the bit-sliced kernels (six-world
- * lists with two variables: two list frames per block, each block decoded
+ * lists with two variables: two list frames per block; each block is decoded
  * once for a group of up to four pairs).  For comparisons, the environment
  * variables KRIPKE_SPLIT_GENERIC=1 (per-lane-frame kernel),
  * KRIPKE_SPLIT_WORLDMASK=1 (world-mask kernel at any size),
  * KRIPKE_SPLIT_ONE_FRAME=1 (one list frame per block) and
- * KRIPKE_LIST_GROUP=1..4 (pairs per group of the two-frame kernel) select
+ * KRIPKE_LIST_GROUP=1..4 (pairs per group of the list kernels) select
  * other kernels; every kernel returns the same keys.
  */
 int kripke_split(const uint8_t *phi, uint32_t len_phi, const uint8_t *psi, uint32_t len_psi,

@@ -34,8 +34,8 @@ struct CensusArgs {
   uint32_t key_pos;            // key frame field = position instead of frame index
 };
 
-// Mode 3 (two list frames per block) scans a group of up to this many formulas
-// per work item, so each block's frames are loaded and decoded once per group.
+// List modes 2 and 3 scan a group of up to this many formulas per work item,
+// so each block's frame rows are loaded and decoded once per group.
 constexpr uint32_t kListGroupMax = 4;
 
 // Arguments of the wave-uniform-frame kernel.  Positions are frame indices
@@ -59,7 +59,7 @@ struct FastArgs {
   uint64_t class_stride;
   uint32_t decide;
   const uint32_t* list_succ;    // modes 2, 3: successor rows [positions][n]
-  uint32_t group;               // mode 3: formulas per work item (1..kListGroupMax)
+  uint32_t group;               // modes 2, 3: formulas per work item (1..kListGroupMax)
   uint32_t* valid_bits;         // optional frame-validity maps [nformulas][valid_words],
   uint64_t valid_words;         // bit p = no countermodel on position p (mode 0)
 };

@@ -545,6 +545,146 @@ __device__ __forceinline__ uint64_t candidate(const Ctx<N, NV, LS, MODE>& c, int
 // Words of one staged program (the micro-ops, 8-byte padded, and slack).
 constexpr int kProgWords = kMaxMicro / 4 + 4;
 
+// Stage the programs of a list work item's formula group (formulas f0 ..
+// f0 + ng - 1 of the launch order) side by side in the wave's LDS area.  A
+// formula whose known key precedes the item's first position p0, or whose
+// program is TOP (no countermodel), takes no part; live gets bit j for the
+// others, bot bit j for a BOT program (false everywhere, not interpreted).
+template <int V>
+__device__ __forceinline__ void stage_group(const FastArgs& a, uint32_t (*progs)[kProgWords],
+                                            uint32_t* pws, uint32_t f0, uint32_t ng,
+                                            uint64_t p0, int lane, uint32_t& live,
+                                            uint32_t& bot) {
+  live = 0;
+  bot = 0;
+  for (uint32_t j = 0; j < ng; ++j) {
+    const uint32_t f = a.order[f0 + j];
+    uint64_t known = __hip_atomic_load(a.out_key + (uint64_t)f * a.out_stride, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+    known = readlane64(known, 0);
+    if (known != ~0ull && (known >> (V + 4)) < p0) continue;
+    const uint32_t q0 = a.uoff[f] >> 2, pw = (a.uoff[f + 1] >> 2) - q0;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.ucode) + q0;
+    for (uint32_t i = lane; i < pw; i += 64) progs[j][i] = src[i];
+    const uint64_t first = ((uint64_t)__builtin_amdgcn_readfirstlane(src[1]) << 32) |
+                           __builtin_amdgcn_readfirstlane(src[0]);
+    if (first == (uint64_t)(U_LOAD + L_TOP)) continue;
+    if (first == (uint64_t)(U_LOAD + L_BOT)) bot |= 1u << j;
+    if (lane == 0) pws[j] = pw;
+    live |= 1u << j;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One work item of mode 2: a range of one-frame list blocks for a group of up
+// to kListGroupMax formulas, first keys only.  Each block's frame rows are
+// read once (scalar loads) and decoded once; every formula of the group
+// without a key then runs its valuation chunks in increasing order, and the
+// first chunk with a failure holds the frame's least key for that formula
+// (chunk bits are the highest valuation bits): the key goes out at once and
+// the formula leaves the group.
+template <int N, int NV, int LS>
+__device__ __forceinline__ void list_item(const FastArgs& a, Ctx<N, NV, LS, 2>& c,
+                                          uint32_t (*progs)[kProgWords], uint32_t* pws,
+                                          uint64_t item, int lane) {
+  using G = Geo<N, NV, LS, 2>;
+  static_assert(G::B == 0, "a list block is one list position");
+  const uint64_t blk_end = a.blk_begin + a.nblk;
+  const uint32_t f0 = (uint32_t)(item / a.items_per_formula) * a.group;
+  const uint32_t ng = a.nformulas - f0 < a.group ? a.nformulas - f0 : a.group;
+  const uint64_t b0 = a.blk_begin + (item % a.items_per_formula) * a.blocks_per_item;
+  const uint64_t b1 = b0 + a.blocks_per_item < blk_end ? b0 + a.blocks_per_item : blk_end;
+  uint32_t live = 0, bot = 0;
+  const uint64_t p0 = b0 > a.pos_begin ? b0 : a.pos_begin;
+  stage_group<G::V>(a, progs, pws, f0, ng, p0, lane, live, bot);
+
+  for (uint64_t blk = b0; blk < b1 && live; ++blk) {
+    // the frame's successor rows, wave-uniform: the list is read-only for the
+    // kernel's lifetime, so reading it through the constant address space
+    // gives scalar loads straight into SGPRs
+    const __attribute__((address_space(4))) uint32_t* rows =
+        (const __attribute__((address_space(4))) uint32_t*)(uintptr_t)(a.list_succ + blk * N);
+    uint64_t base = 0;
+#pragma unroll
+    for (int w = 0; w < N; ++w) base |= (uint64_t)rows[w] << (w * N);
+    // the first RV_ROWS rows in vector registers, one signed bit-field
+    // extract per word (opaque, so the words stay vector values); the others
+    // stay scalar
+    uint32_t vbase[2] = {0u, 0u};
+    if constexpr (G::RUV) {
+      asm volatile("v_mov_b32 %0, %1" : "=v"(vbase[0]) : "s"((uint32_t)base));
+      if constexpr (N * G::RV_ROWS > 32)
+        asm volatile("v_mov_b32 %0, %1" : "=v"(vbase[1]) : "s"((uint32_t)(base >> 32)));
+    }
+#pragma unroll
+    for (int w = 0; w < N; ++w)
+#pragma unroll
+      for (int v = 0; v < N; ++v) {
+        const int p = w * N + v;
+        if (w < G::RV_ROWS) {
+          uint32_t r;
+          asm volatile("v_bfe_i32 %0, %1, %2, 1" : "=v"(r) : "v"(vbase[p >> 5]), "i"(p & 31));
+          c.ru[w][v] = r;
+        } else if (N * N <= 32) {
+          c.ru[w][v] = (uint32_t)__builtin_amdgcn_sbfe((int)(uint32_t)base, p, 1);
+        } else {
+          c.ru[w][v] = 0u - (uint32_t)((base >> p) & 1u);
+        }
+      }
+    for (uint32_t j = 0; j < ng; ++j) {
+      if (!((live >> j) & 1u)) continue;
+      const uint32_t* prog = progs[j];
+      for (uint32_t chunk = 0; chunk < (1u << G::CHB); ++chunk) {
+#pragma unroll
+        for (int i = 0; i < G::CHB; ++i)
+          c.ch[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)(0u - ((chunk >> i) & 1u)));
+        if ((bot >> j) & 1u) {
+#pragma unroll
+          for (int s = 0; s < G::S; ++s)
+#pragma unroll
+            for (int w = 0; w < N; ++w) c.acc[s][w] = 0u;
+        } else {
+          const uint64_t first = ((uint64_t)__builtin_amdgcn_readfirstlane(prog[1]) << 32) |
+                                 __builtin_amdgcn_readfirstlane(prog[0]);
+          run<N, NV, LS, 2>(c, prog, first, (uint32_t)__builtin_amdgcn_readfirstlane(pws[j]) >> 1);
+        }
+        // any failure on this lane: one AND over every set's words
+        uint32_t holds = ~0u;
+#pragma unroll
+        for (int s = 0; s < G::S; ++s)
+#pragma unroll
+          for (int w = 0; w < N; ++w) holds &= c.acc[s][w];
+        if (!__ballot(holds != ~0u)) continue;
+        // the least key lies in the first failing set (sets are valuation
+        // bits above the lane bits)
+        uint64_t best = ~0ull;
+        bool found = false;
+#pragma unroll
+        for (int s = 0; s < G::S; ++s) {
+          if (!found) {
+            uint32_t all = ~0u;
+#pragma unroll
+            for (int w = 0; w < N; ++w) all &= c.acc[s][w];
+            const uint32_t fail = ~all;
+            const uint64_t bal = __ballot(fail != 0);
+            if (bal) {
+              best = candidate(c, s, fail, bal, blk, chunk, lane);
+              found = true;
+            }
+          }
+        }
+        if (lane == 0)
+          atomicMin(a.out_key + (uint64_t)a.order[f0 + j] * a.out_stride,
+                    (unsigned long long)best);
+        live = (uint32_t)__builtin_amdgcn_readfirstlane((int)(live & ~(1u << j)));
+        break;
+      }
+    }
+  }
+}
+
 // One work item of mode 3: a range of two-frame blocks for a group of up to
 // kListGroupMax formulas (consecutive in the launch order), first keys only.
 // The group's programs are staged side by side in the wave's LDS area; each
@@ -567,28 +707,8 @@ __device__ __forceinline__ void list2_item(const FastArgs& a, Ctx<N, NV, LS, 3>&
   const uint64_t b1 = b0 + a.blocks_per_item < blk_end ? b0 + a.blocks_per_item : blk_end;
   const uint64_t p0 = (b0 << G::B) > a.pos_begin ? (b0 << G::B) : a.pos_begin;
 
-  // stage the group's programs; a formula whose known key precedes the range,
-  // or whose program is TOP (no countermodel), takes no part
   uint32_t live = 0, bot = 0;
-  for (uint32_t j = 0; j < ng; ++j) {
-    const uint32_t f = a.order[f0 + j];
-    uint64_t known = __hip_atomic_load(a.out_key + (uint64_t)f * a.out_stride, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-    known = readlane64(known, 0);
-    if (known != ~0ull && (known >> (G::V + 4)) < p0) continue;
-    const uint32_t q0 = a.uoff[f] >> 2, pw = (a.uoff[f + 1] >> 2) - q0;
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.ucode) + q0;
-    for (uint32_t i = lane; i < pw; i += 64) progs[j][i] = src[i];
-    const uint64_t first = ((uint64_t)__builtin_amdgcn_readfirstlane(src[1]) << 32) |
-                           __builtin_amdgcn_readfirstlane(src[0]);
-    if (first == (uint64_t)(U_LOAD + L_TOP)) continue;
-    if (first == (uint64_t)(U_LOAD + L_BOT)) bot |= 1u << j;
-    if (lane == 0) pws[j] = pw;
-    live |= 1u << j;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  stage_group<G::V>(a, progs, pws, f0, ng, p0, lane, live, bot);
 
   for (uint64_t blk = b0; blk < b1 && live; ++blk) {
     // each half-wave's frame (position blk << B | lane_pos; a position past
@@ -638,9 +758,13 @@ __device__ __forceinline__ void list2_item(const FastArgs& a, Ctx<N, NV, LS, 3>&
         for (int w = 0; w < N; ++w) all &= c.acc[s][w];
         return in_range ? ~all : 0u;
       };
-      uint32_t anyfail = 0;
+      // any failure on this lane: one AND over every set's words
+      uint32_t holds = ~0u;
 #pragma unroll
-      for (int s = 0; s < G::S; ++s) anyfail |= fail_of(s);
+      for (int s = 0; s < G::S; ++s)
+#pragma unroll
+        for (int w = 0; w < N; ++w) holds &= c.acc[s][w];
+      const uint32_t anyfail = in_range ? ~holds : 0u;
       if (!__ballot(anyfail != 0)) continue;
       // the first half-wave's frame precedes every valuation of the second:
       // the sets are searched on its lanes first, then on the whole wave
@@ -679,8 +803,8 @@ void census_fast(FastArgs a) {
   static_assert(!G::LIST || (G::V >= 5 + G::LV + LS && !FUSED),
                 "list mode needs the lane and set bits to be valuation bits");
   // staged programs: one per wave, a group of them in mode 3
-  __shared__ uint32_t sprog[4][G::LIST2 ? kListGroupMax : 1][kProgWords];
-  __shared__ uint32_t spw[4][G::LIST2 ? kListGroupMax : 1];
+  __shared__ uint32_t sprog[4][G::LIST ? kListGroupMax : 1][kProgWords];
+  __shared__ uint32_t spw[4][G::LIST ? kListGroupMax : 1];
   __shared__ uint32_t sspill[4][G::LDS_WORDS > 0 ? G::LDS_WORDS * 64 : 1];
   // fused mode: per-lane failure counts of the classes T, S4, S5, private to
   // the lane (only blocks that can hold a reflexive frame touch them, so they
@@ -722,8 +846,11 @@ void census_fast(FastArgs a) {
       list2_item<N, NV, LS>(a, c, sprog[threadIdx.x >> 6], spw[threadIdx.x >> 6], item, lane,
                             rag_lo, rag_hi);
       continue;
+    } else if constexpr (G::LIST) {
+      list_item<N, NV, LS>(a, c, sprog[threadIdx.x >> 6], spw[threadIdx.x >> 6], item, lane);
+      continue;
     }
-    // (mode 3 items never reach this point)
+    // (list-mode items never reach this point)
     const uint32_t f = a.order[item / a.items_per_formula];
     const uint64_t b0 = a.blk_begin + (item % a.items_per_formula) * a.blocks_per_item;
     const uint64_t b1 = b0 + a.blocks_per_item < blk_end ? b0 + a.blocks_per_item : blk_end;
@@ -770,20 +897,7 @@ void census_fast(FastArgs a) {
 
     for (uint64_t blk = b0; blk < b1 && !done; ++blk) {
       const uint64_t pbase = blk << G::B;
-      uint64_t base = 0;
-      if constexpr (G::LIST) {
-        // the list frame's successor rows, wave-uniform
-        // the list is read-only for the kernel's lifetime: reading it through
-        // the constant address space gives scalar loads straight into SGPRs
-        // instead of a vector load and a wait on every frame
-        const __attribute__((address_space(4))) uint32_t* rows =
-            (const __attribute__((address_space(4))) uint32_t*)(uintptr_t)(a.list_succ + blk * N);
-        base = 0;
-#pragma unroll
-        for (int w = 0; w < N; ++w) base |= (uint64_t)rows[w] << (w * N);
-      } else {
-        base = MODE == 0 ? pbase : refl_frame(pbase, N);
-      }
+      const uint64_t base = MODE == 0 ? pbase : refl_frame(pbase, N);
       // the relation bits in vector registers, expanded there by one signed
       // bit-field extract per word (opaque, so the words stay vector values)
       uint32_t vbase[2] = {0u, 0u};
@@ -809,7 +923,7 @@ void census_fast(FastArgs a) {
           }
         }
       // valid (lane, set) pairs: positions inside [pos_begin, pos_end)
-      const bool ragged = !G::LIST && (blk == rag_lo || blk == rag_hi);
+      const bool ragged = blk == rag_lo || blk == rag_hi;
       // class levels of the block's frames; consumed only after evaluation,
       // so the scalar load overlaps the interpreter
       uint32_t lvl_raw = 0;
@@ -840,7 +954,7 @@ void census_fast(FastArgs a) {
           for (int w = 0; w < N; ++w) all &= c.acc[s][w];
           uint32_t fail = ~all;  // an all-fail program's accumulator is zero
           if (ragged) {
-            const uint64_t pos = pbase | (G::LIST ? 0ull : (uint64_t)s << G::LF) | lane_pos;
+            const uint64_t pos = pbase | ((uint64_t)s << G::LF) | lane_pos;
             if (pos < a.pos_begin || pos >= a.pos_end) fail = 0;
           }
           return fail;
@@ -906,8 +1020,7 @@ void census_fast(FastArgs a) {
           }
         }
         // one ballot per block while no key is known; then the least key lies in
-        // the first failing set (sets follow frame positions, or, in list mode,
-        // valuation bits above the lane bits)
+        // the first failing set (sets follow frame positions)
         if (key[0] == ~0ull && __ballot(anyfail != 0)) {
           bool found = false;
 #pragma unroll
@@ -923,10 +1036,6 @@ void census_fast(FastArgs a) {
             }
           }
         }
-        // list mode: chunks run in increasing valuation order inside one
-        // frame, so the first chunk with a failure holds the frame's least key
-        if constexpr (G::LIST)
-          if (a.decide && best[0] != ~0ull) break;
       }
 #pragma unroll
       for (int k = 0; k < NC; ++k)

@@ -442,11 +442,11 @@ int enqueue_fast(DeviceState* ds, const DeviceBatch& db, int n, int nvars, int l
   // keys of consecutive formulas (2 for census results, 1 for split keys);
   // list_succ: the frame list of modes 2 and 3
   if (row_formulas == 0) row_formulas = nformulas;
-  // mode 3 scans groups of formulas per work item and searches first keys only
+  // list modes scan groups of formulas per work item and search first keys only
   uint32_t group = 1;
-  if (mode == 3) {
+  if (mode >= 2) {
     if (!decide || cnt || valid_bits)
-      return fail(KRIPKE_EINTERNAL, "two-frame list blocks search first keys only");
+      return fail(KRIPKE_EINTERNAL, "list-mode blocks search first keys only");
     group = kListGroupMax;
     if (const char* env = getenv("KRIPKE_LIST_GROUP"))
       group = (uint32_t)std::min<long>(kListGroupMax, std::max<long>(1, atol(env)));
@@ -468,7 +468,7 @@ int enqueue_fast(DeviceState* ds, const DeviceBatch& db, int n, int nvars, int l
   uint64_t bpi = std::max<uint64_t>(1, (a.nblk * ngroups + target - 1) / target);
   bpi = std::min<uint64_t>(bpi, 1ull << 16);
   a.blocks_per_item = bpi;
-  a.items_per_formula = (a.nblk + bpi - 1) / bpi;  // per group in mode 3
+  a.items_per_formula = (a.nblk + bpi - 1) / bpi;  // per group in list modes
   a.total_items = a.items_per_formula * ngroups;
   a.group = group;
   a.queue = queue;
