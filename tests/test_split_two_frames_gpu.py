@@ -89,8 +89,8 @@ def test_formula_groups_match_single_formulas(kr, monkeypatch, nframes):
         assert np.array_equal(kr.split(pairs, frames, 6), single), (g, nframes)
 
 
-@pytest.mark.parametrize("n", [7, 8])
-def test_one_frame_list_groups_match_single_formulas(kr, monkeypatch, n):
+@pytest.mark.parametrize("n,nframes", [(7, 777), (8, 777), (7, 1), (8, 2)])
+def test_one_frame_list_groups_match_single_formulas(kr, monkeypatch, n, nframes):
     """The one-frame list kernels (seven and eight worlds) also scan groups of pairs per
     work item, each pair running its valuation chunks in order on the decoded frame: every
     group size gives the keys of one pair per item, with deep pairs in the second tier,
@@ -98,7 +98,7 @@ def test_one_frame_list_groups_match_single_formulas(kr, monkeypatch, n):
     p = I.parse("p")
     pairs = _pairs()[:150] + [([I.TOP], [I.BOT]), (p, p), ([I.BOT], [I.BOT])]
     pairs += _pairs()[-10:]
-    frames = I.frame_family(n, 777)
+    frames = I.frame_family(n, nframes)
     monkeypatch.setenv("KRIPKE_LIST_GROUP", "1")
     single = kr.split(pairs, frames, n)
     assert single[150] == 0 and single[151] == kr.NO_KEY
